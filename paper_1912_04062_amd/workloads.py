@@ -1,0 +1,103 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws random numbers and assembles test matrices; it holds
+none of the eigensolver's arithmetic.  It is shared by the tests, the smoke
+check and the benchmark (GPU side and oracle side alike).
+
+* ``random_skew``   - dense A = (B - B^T)/2 with B iid N(0, 1): the random
+                       double-precision skew-symmetric matrices of the paper's
+                       ELPA benchmarks (Section 4.1).
+* ``prescribed``    - A = Q blockdiag([[0, l_k], [-l_k, 0]]) Q^T with Q Haar
+                       orthogonal and l_k log-uniform: known spectrum +-i*l_k
+                       and known eigenvectors (q_2k + i q_2k+1)/sqrt(2).
+* ``bse_shaped``    - the skew matrix L^T J L of the Bethe-Salpeter route
+                       (Section 3: M = J H > 0, Cholesky M = L L^T), built from
+                       a synthetic real M = [[A, B], [B, A]].  It stands in for
+                       the hexagonal boron nitride Hamiltonian of Section 4.2,
+                       which is not available.
+* ``batch_sizes``   - matrix orders for a batch of uneven problems.
+
+All matrices are returned as Fortran-ordered (column-major) float64 arrays.
+"""
+import numpy as np
+
+
+def random_skew(n, seed):
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((n, n))
+    A = np.asfortranarray((B - B.T) * 0.5)
+    return A
+
+
+def haar_orthogonal(n, rng):
+    """Haar-distributed orthogonal matrix: QR of a Gaussian matrix with the
+    signs of R's diagonal moved into Q (Mezzadri 2007)."""
+    G = rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(G)
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Q * s[None, :]
+
+
+def prescribed(n, seed, lo=1e-3, hi=10.0):
+    """Skew matrix with prescribed spectrum.
+
+    Returns (A, l, Q): l (ascending, length n//2) are the positive eigenvalue
+    magnitudes, Q the orthogonal basis; for odd n the last column of Q spans
+    the null space.  The eigenvector of +i*l[k] is (Q[:, 2p] + i Q[:, 2p+1])/sqrt(2)
+    where p is the block index of l[k] (blocks are laid out in ascending order).
+    """
+    rng = np.random.default_rng(seed)
+    Q = haar_orthogonal(n, rng)
+    m = n // 2
+    l = np.sort(10.0 ** rng.uniform(np.log10(lo), np.log10(hi), size=m))
+    S = np.zeros((n, n))
+    for p in range(m):
+        S[2 * p, 2 * p + 1] = l[p]
+        S[2 * p + 1, 2 * p] = -l[p]
+    A = Q @ S @ Q.T
+    A = np.asfortranarray((A - A.T) * 0.5)
+    return A, l, Q
+
+
+def bse_blocks(m, seed, rank=64):
+    """Real symmetric blocks A = diag(d) + V V^T/m, B = 0.1 W W^T/m."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(1.0, 10.0, size=m)
+    V = rng.standard_normal((m, rank))
+    W = rng.standard_normal((m, rank))
+    Ab = np.diag(d) + V @ V.T / m
+    Bb = 0.1 * (W @ W.T) / m
+    return Ab, Bb
+
+
+def bse_shaped(m, seed, rank=64):
+    """K = L^T J L with M = [[A, B], [B, A]] = L L^T (n = 2m).
+
+    Returns (K, Ab, Bb).  The spectrum of K is +-i*sqrt(eig((A+B)(A-B))).
+    """
+    Ab, Bb = bse_blocks(m, seed, rank)
+    M = np.block([[Ab, Bb], [Bb, Ab]])
+    L = np.linalg.cholesky(M)
+    n = 2 * m
+    # J L = [[L_bottom], [-L_top]]  (J = [[0, I], [-I, 0]])
+    JL = np.vstack([L[m:, :], -L[:m, :]])
+    K = L.T @ JL
+    K = np.asfortranarray((K - K.T) * 0.5)
+    return K, Ab, Bb
+
+
+def batch_sizes(count, seed, lo=64, hi=1024):
+    rng = np.random.default_rng(seed)
+    return [int(x) for x in rng.integers(lo, hi, size=count, endpoint=True)]
+
+
+def batch(count, seed, lo=64, hi=1024):
+    """A batch of random skew matrices of uneven order (one generator stream)."""
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in rng.integers(lo, hi, size=count, endpoint=True)]
+    mats = []
+    for n in sizes:
+        B = rng.standard_normal((n, n))
+        mats.append(np.asfortranarray((B - B.T) * 0.5))
+    return sizes, mats

@@ -1,0 +1,313 @@
+"""Pins for the oracle: facts fixed by the paper and by mathematics, not by
+the oracle itself.  CPU only.
+
+Each test names what it pins.  Together they catch the plausible mistakes in
+the oracle: a wrong sign of alpha (Lemma 1 needs the super-diagonal, else
+every eigenvector is that of -i*lambda), a dropped term of the rank-2 update
+(wrong eigenvalues), a transposed back-transformation (large residuals), a
+wrong D indexing (eigenvectors of the wrong sign pattern), a wrong Sturm
+recurrence (wrong eigenvalues) and a broken odd-order case.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1912_04062_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _tsym(alpha):
+    n = len(alpha) + 1
+    T = np.zeros((n, n))
+    for j, a in enumerate(alpha):
+        T[j, j + 1] = T[j + 1, j] = a
+    return T
+
+
+def _metrics(A, lam, Z):
+    n = A.shape[0]
+    nA = max(float(np.max(np.abs(np.linalg.eigvalsh(-1j * A)))), 1e-300)
+    res = np.linalg.norm(A @ Z - Z * (1j * lam)[None, :]) / (n * nA)
+    orth = np.linalg.norm(Z.conj().T @ Z - np.eye(Z.shape[1])) / n
+    return res, orth, nA
+
+
+# ---------------------------------------------------------------------------
+# Whole solver against a brute-force Hermitian eigensolve of -iA (tiny n).
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 13, 32, 33, 64])
+@pytest.mark.parametrize("seed", [1, 11])
+def test_tiny_vs_hermitian(oracle_mod, n, seed):
+    A = wl.random_skew(n, seed)
+    lam, Z = oracle_mod.skew_evd(A)
+    assert lam.shape == ((n + 1) // 2,)
+    mu, U = np.linalg.eigh(-1j * A)          # -iA u = mu u  <=>  A u = i mu u
+    ref = mu[n // 2:]
+    nA = max(np.abs(mu).max(), 1.0 if n < 2 else 0.0)
+    assert np.all(lam >= 0)
+    assert np.max(np.abs(lam - ref)) <= 1e-13 * nA
+    res, orth, _ = _metrics(A, lam, Z) if n > 1 else (0.0, 0.0, 1.0)
+    assert res <= 1e-14 and orth <= 1e-14
+    # eigenvector subspaces, phase-invariantly, for well separated eigenvalues
+    for k in range(len(lam)):
+        gaps = np.abs(mu - mu[n // 2 + k])
+        gaps[n // 2 + k] = np.inf
+        if gaps.min() > 1e-6 * nA:
+            u = U[:, n // 2 + k]
+            assert abs(np.vdot(u, Z[:, k])) >= 1 - 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Prescribed spectrum: exact eigenvalues l_k and eigenvectors (q_2p + i q_2p+1)/sqrt(2).
+@pytest.mark.parametrize("n", [16, 200, 301])
+def test_prescribed_spectrum(oracle_mod, n):
+    A, l, Q = wl.prescribed(n, 2)
+    lam, Z = oracle_mod.skew_evd(A)
+    ref = np.concatenate([[0.0] if n % 2 else [], l])
+    assert np.max(np.abs(lam - ref)) <= 1e-12 * l.max()
+    off = 1 if n % 2 else 0
+    for p in range(len(l)):
+        z_ref = (Q[:, 2 * p] + 1j * Q[:, 2 * p + 1]) / np.sqrt(2.0)
+        lo = l[p - 1] if p > 0 else -np.inf
+        hi = l[p + 1] if p + 1 < len(l) else np.inf
+        gap = min(l[p] - lo, hi - l[p]) / l.max()
+        if gap > 1e-6:
+            # +i*lambda eigenvector; the conjugate (wrong sign of alpha) gives 0 here
+            assert abs(np.vdot(z_ref, Z[:, off + p])) >= 1 - 1e-8
+
+
+def test_prescribed_sign_discriminates():
+    """The pin above separates z from conj(z): |<z, conj z>| = 0 for these vectors."""
+    _, _, Q = wl.prescribed(8, 3)
+    z = (Q[:, 0] + 1j * Q[:, 1]) / np.sqrt(2.0)
+    assert abs(np.vdot(z, z.conj())) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Tridiagonal solver: closed forms.
+def test_golden_clement_n8(oracle_mod):
+    with open(os.path.join(GOLDEN, "clement_n8.txt")) as f:
+        rows = [r for r in f.read().splitlines() if r and not r.startswith("#")]
+    a2 = np.array([float(x) for x in rows[0].split()])
+    ev = np.array([float(x) for x in rows[1].split()])
+    alpha = np.sqrt(a2)
+    w = oracle_mod.tridiag_eigvals(alpha, 4, 4)
+    assert np.max(np.abs(w - ev)) <= 1e-13 * 8
+
+
+@pytest.mark.parametrize("n", [9, 10, 100, 101, 512])
+def test_clement(oracle_mod, n):
+    j = np.arange(1, n)
+    alpha = np.sqrt(j * (n - j).astype(float))
+    half = (n + 1) // 2
+    w = oracle_mod.tridiag_eigvals(alpha, n // 2, half)
+    exact = np.sort(np.array([n - 1 - 2 * k for k in range(n)], float))[n // 2:]
+    assert np.max(np.abs(w - exact)) <= 4e-15 * n * (n - 1)
+    Q = oracle_mod.tridiag_eigvecs(alpha, w)
+    T = _tsym(alpha)
+    assert np.linalg.norm(T @ Q - Q * w[None, :]) <= 1e-13 * n * n
+    assert np.linalg.norm(Q.T @ Q - np.eye(half)) <= 1e-13 * n
+
+
+@pytest.mark.parametrize("n", [2, 7, 64, 257])
+def test_all_ones(oracle_mod, n):
+    alpha = np.ones(n - 1)
+    k = np.arange(1, n + 1)
+    exact = np.sort(2 * np.cos(k * np.pi / (n + 1)))[n // 2:]
+    if n % 2:
+        exact[0] = 0.0
+    w = oracle_mod.tridiag_eigvals(alpha, n // 2, (n + 1) // 2)
+    assert np.max(np.abs(w - exact)) <= 1e-14 * 4
+
+
+@pytest.mark.parametrize("n", [2, 6, 50, 51, 300])
+def test_bidiagonal_singular_values(oracle_mod, n):
+    """T_sym with zero diagonal is the Golub-Kahan form of B = T[0::2, 1::2]:
+    its non-negative eigenvalues are B's singular values (plus 0 for odd n)."""
+    rng = np.random.default_rng(n)
+    alpha = rng.standard_normal(n - 1)
+    T = _tsym(alpha)
+    B = T[0::2, 1::2]
+    s = np.linalg.svd(B, compute_uv=False)
+    ref = np.sort(np.concatenate([s, np.zeros((n + 1) // 2 - len(s))]))
+    w = oracle_mod.tridiag_eigvals(alpha, n // 2, (n + 1) // 2)
+    assert np.max(np.abs(w - ref)) <= 1e-14 * max(1.0, np.abs(alpha).max()) * 8
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12])
+def test_sturm_bruteforce(oracle_mod, n):
+    rng = np.random.default_rng(100 + n)
+    for _ in range(5):
+        alpha = rng.standard_normal(n - 1)
+        ev = np.linalg.eigvalsh(_tsym(alpha)) if n > 1 else np.zeros(1)
+        for x in rng.uniform(-3, 3, size=20):
+            if np.min(np.abs(ev - x)) < 1e-9:
+                continue
+            assert oracle_mod.sturm_count(alpha, x) == int(np.sum(ev < x))
+
+
+def test_golden_lemma1():
+    """Lemma 1 itself (the identity the oracle's step 2 rests on)."""
+    with open(os.path.join(GOLDEN, "lemma1_n4.txt")) as f:
+        rows = [r for r in f.read().splitlines() if r and not r.startswith("#")]
+    alpha = np.array([float(x) for x in rows[0].split()])
+    Tsk = np.array([[float(x) for x in r.split()] for r in rows[1:5]])
+    Tsy = np.array([[float(x) for x in r.split()] for r in rows[5:9]])
+    D = np.diag(1j ** np.arange(4))
+    assert np.allclose(-1j * D.conj().T @ Tsk @ D, Tsy, atol=0, rtol=0) or \
+        np.max(np.abs(-1j * D.conj().T @ Tsk @ D - Tsy)) < 1e-15
+    assert np.allclose(np.diag(Tsy, 1), alpha)
+
+
+# ---------------------------------------------------------------------------
+# Odd order: an exact zero eigenvalue with a real eigenvector.
+@pytest.mark.parametrize("n", [3, 9, 101, 255])
+def test_odd_null_vector(oracle_mod, n):
+    A = wl.random_skew(n, 5)
+    lam, Z = oracle_mod.skew_evd(A)
+    assert lam[0] == 0.0
+    assert np.all(Z[:, 0].imag == 0.0)
+    nA = lam.max()
+    assert np.linalg.norm(A @ Z[:, 0].real) <= 1e-13 * nA * np.sqrt(n)
+    assert abs(np.linalg.norm(Z[:, 0]) - 1) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Bethe-Salpeter: eig(L^T J L) = +-i sqrt(eig((A+B)(A-B))) (Section 3, M = JH).
+@pytest.mark.parametrize("m", [20, 50])
+def test_bse_eigenvalues(oracle_mod, m):
+    K, Ab, Bb = wl.bse_shaped(m, 3, rank=8)
+    lam, Z = oracle_mod.skew_evd(K)
+    Lp = np.linalg.cholesky(Ab + Bb)
+    ref = np.sqrt(np.sort(np.linalg.eigvalsh(Lp.T @ (Ab - Bb) @ Lp)))
+    assert np.max(np.abs(lam - ref)) <= 1e-13 * ref.max()
+    res, orth, _ = _metrics(K, lam, Z)
+    assert res <= 1e-14 and orth <= 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Invariants.
+@pytest.mark.parametrize("n", [10, 63, 128])
+def test_invariants(oracle_mod, n):
+    A = wl.random_skew(n, 9)
+    lam, Z = oracle_mod.skew_evd(A)
+    fro2 = np.sum(A * A)
+    assert abs(2 * np.sum(lam ** 2) - fro2) <= 1e-13 * fro2
+    alpha, V, tau = oracle_mod.tridiagonalize(A)
+    assert abs(2 * np.sum(alpha ** 2) - fro2) <= 1e-13 * fro2
+    # Re z and Im z: equal norms and orthogonal (z^T z = 0 for lambda > 0)
+    for k in range(len(lam)):
+        if lam[k] > 1e-8:
+            zr, zi = Z[:, k].real, Z[:, k].imag
+            assert abs(np.linalg.norm(zr) - np.sqrt(0.5)) < 1e-12
+            assert abs(np.linalg.norm(zi) - np.sqrt(0.5)) < 1e-12
+            assert abs(zr @ zi) < 1e-12
+
+
+def test_tridiagonalization_similarity(oracle_mod):
+    """Q_trd^T A Q_trd is the skew tridiagonal with super-diagonal alpha."""
+    n = 40
+    A = wl.random_skew(n, 21)
+    alpha, V, tau = oracle_mod.tridiagonalize(A)
+    Q = np.eye(n)
+    for j in range(n - 2):
+        v = V[:, j]
+        Q = Q @ (np.eye(n) - tau[j] * np.outer(v, v))
+    T = Q.T @ A @ Q
+    Tref = np.diag(alpha, 1) - np.diag(alpha, -1)
+    assert np.max(np.abs(T - Tref)) <= 1e-13 * np.abs(A).max() * n
+
+
+# ---------------------------------------------------------------------------
+# Special cases.
+def test_n0(oracle_mod):
+    lam, Z = oracle_mod.skew_evd(np.zeros((0, 0)))
+    assert lam.size == 0
+
+
+def test_n1(oracle_mod):
+    lam, Z = oracle_mod.skew_evd(np.zeros((1, 1)))
+    assert lam[0] == 0.0 and abs(Z[0, 0]) == 1.0
+
+
+@pytest.mark.parametrize("l", [2.5, -0.75])
+def test_n2(oracle_mod, l):
+    A = np.array([[0.0, -l], [l, 0.0]], order="F")
+    lam, Z = oracle_mod.skew_evd(A)
+    assert abs(lam[0] - abs(l)) <= 1e-15 * abs(l)
+    z = Z[:, 0]
+    ref = np.array([1.0, -1j * np.sign(l)]) / np.sqrt(2.0)
+    assert abs(abs(np.vdot(ref, z)) - 1) < 1e-15
+
+
+@pytest.mark.parametrize("n", [6, 7])
+def test_zero_matrix(oracle_mod, n):
+    A = np.zeros((n, n), order="F")
+    lam, Z = oracle_mod.skew_evd(A)
+    assert np.all(lam == 0.0)
+    assert np.linalg.norm(Z.conj().T @ Z - np.eye(Z.shape[1])) < 1e-14
+
+
+def test_already_tridiagonal(oracle_mod):
+    n = 30
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal(n - 1)
+    A = np.asfortranarray(np.diag(a, 1) - np.diag(a, -1))
+    lam, Z = oracle_mod.skew_evd(A)
+    alpha, V, tau = oracle_mod.tridiagonalize(A)
+    assert np.all(tau == 0.0)
+    res, orth, nA = _metrics(A, lam, Z)
+    assert res <= 1e-14 and orth <= 1e-14
+    mu = np.linalg.eigvalsh(-1j * A)[n // 2:]
+    assert np.max(np.abs(lam - mu)) <= 1e-13 * nA
+
+
+def test_banded_input(oracle_mod):
+    n, b = 40, 5
+    A = wl.random_skew(n, 8)
+    for i in range(n):
+        for j in range(n):
+            if abs(i - j) > b:
+                A[i, j] = 0.0
+    lam, Z = oracle_mod.skew_evd(A)
+    mu = np.linalg.eigvalsh(-1j * A)[n // 2:]
+    assert np.max(np.abs(lam - mu)) <= 1e-13 * mu.max()
+
+
+def test_only_lower_triangle_read(oracle_mod):
+    n = 17
+    A = wl.random_skew(n, 6)
+    B = A.copy(order="F")
+    B[np.triu_indices(n)] = 123.0          # garbage on and above the diagonal
+    l1, Z1 = oracle_mod.skew_evd(A)
+    l2, Z2 = oracle_mod.skew_evd(B)
+    assert np.array_equal(l1, l2) and np.array_equal(Z1, Z2)
+
+
+def test_partial_nev(oracle_mod):
+    n = 50
+    A = wl.random_skew(n, 12)
+    lam_all, Z_all = oracle_mod.skew_evd(A)
+    lam, Z = oracle_mod.skew_evd(A, nev=7)
+    assert np.array_equal(lam, lam_all[:7])
+
+
+def test_status_codes(oracle_mod):
+    A = wl.random_skew(8, 1)
+    assert oracle_mod.skew_evd_status(A, 5) == -4
+    assert oracle_mod.skew_evd_status(A, -1) == -4
+    B = A.copy(order="F")
+    B[5, 2] = np.nan
+    assert oracle_mod.skew_evd_status(B, 4) == 1
+    B[5, 2] = 0.0
+    B[2, 5] = np.nan                          # upper triangle is not read
+    assert oracle_mod.skew_evd_status(B, 4) == 0
+
+
+def test_golden_oracle_regression(oracle_mod):
+    with open(os.path.join(GOLDEN, "oracle_random_n12_seed7.txt")) as f:
+        rows = [r for r in f.read().splitlines() if r and not r.startswith("#")]
+    ref = np.array([float(x) for x in rows[0].split()])
+    lam, _ = oracle_mod.skew_evd(wl.random_skew(12, 7))
+    assert np.max(np.abs(lam - ref)) <= 1e-14 * ref.max()
