@@ -1,0 +1,159 @@
+/*
+ * skew_evd.h - dense real skew-symmetric eigensolver for AMD MI355X (gfx950).
+ *
+ * Problem (Penke, Marek, Vorwerk, Draxl, Benner, "High Performance Solution of
+ * Skew-symmetric Eigenvalue Problems with Applications in Solving the
+ * Bethe-Salpeter Eigenvalue Problem", Section 2.2, Algorithm 1): for a real
+ * A = -A^T of order n, find real lambda_k and unitary Q with
+ * Q^H A Q = diag(i lambda_k).  The eigenvalues come in pairs +-i lambda and the
+ * eigenvectors of a pair are complex conjugates (Section 2.1), so only the
+ * non-negative half is computed.
+ *
+ * Method (Sections 2.1-2.3): two-stage tridiagonalization (blocked Householder
+ * full-to-band reduction with skew rank-2b updates A += V W^T - W V^T, then
+ * band-to-tridiagonal bulge chasing with skew SYMV/SYR2 on the diagonal
+ * blocks), the symmetric tridiagonal eigenproblem of Lemma 1, the
+ * back-transformation by D = diag(i^k) and the two-stage Householder
+ * back-transformation of the real and imaginary parts.
+ *
+ * Conventions common to every entry point:
+ *  - Matrices are column-major, FP64.  A, lambda, Z_re, Z_im, alpha, band and
+ *    Q arguments are DEVICE pointers (hipMalloc memory, or a PyTorch ROCm
+ *    tensor's data pointer) on the current HIP device.
+ *  - Only the strict lower triangle of A is read (A_ij = -A_ji); the diagonal
+ *    and the upper triangle are ignored.  A is never written.
+ *  - The caller owns every buffer passed in; the library never frees caller
+ *    memory.  A handle owns its internal workspace (grown on demand, freed by
+ *    skew_evd_destroy).
+ *  - Return value: SKEW_EVD_OK (0) on success; -k when argument k (1-based,
+ *    LAPACK info convention) is invalid; a positive SKEW_EVD_* code otherwise.
+ *    Invalid arguments are detected before any device work is queued.
+ */
+#ifndef SKEW_EVD_H
+#define SKEW_EVD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SKEW_EVD_OK 0
+#define SKEW_EVD_ERR_NONFINITE 1   /* NaN or Inf in the strict lower triangle */
+#define SKEW_EVD_ERR_NOCONV 2      /* tridiagonal solver or a device wait did not finish */
+#define SKEW_EVD_WARN_REFINE 3     /* refinement stopped above its tolerance (results valid, best iterate) */
+#define SKEW_EVD_ERR_NOMEM 4       /* workspace allocation failed or exceeds opts.workspace_limit */
+#define SKEW_EVD_ERR_HIP 5         /* HIP runtime error; text from skew_evd_status_string */
+#define SKEW_EVD_ERR_NODEVICE 6    /* no usable gfx950 device */
+
+#define SKEW_EVD_PREC_FP64 0        /* every stage in FP64 */
+#define SKEW_EVD_PREC_FP32_REFINE 1 /* band reduction and back-transformation in FP32
+                                       (FP32 MFMA, FP64 norms), then FP64 refinement */
+
+typedef struct skew_evd_opts {
+    int precision;          /* SKEW_EVD_PREC_*; default FP64 */
+    int band;               /* semi-bandwidth b of the intermediate band matrix
+                               (= panel width of the full-to-band stage); 0 = auto.
+                               Supported: 8..64, multiple of 8 */
+    int max_refine_sweeps;  /* precision form: refinement sweeps (default 2) */
+    double refine_tol;      /* precision form: stop when the normalised
+                               residual estimate is below this (default 1e-14) */
+    size_t workspace_limit; /* bytes; 0 = unlimited.  Exceeding it returns NOMEM */
+    int reserved[8];
+} skew_evd_opts;
+
+typedef struct skew_evd_info {
+    double ms_total;        /* device time of the whole call (HIP events) */
+    double ms_stage[8];     /* 0 ingest, 1 full->band, 2 bulge chase,
+                               3 tridiagonal solve, 4 back-transform stage 2 (incl. D),
+                               5 back-transform stage 1, 6 refinement, 7 copy-out */
+    int band;               /* band width used */
+    int refine_sweeps;      /* sweeps performed (precision form) */
+    double refine_residual; /* last normalised residual estimate (precision form) */
+    size_t workspace_bytes; /* device workspace held by the handle */
+} skew_evd_info;
+
+typedef struct skew_evd_handle_s *skew_evd_handle;
+
+/* Fill *opts with the defaults described above. */
+void skew_evd_default_opts(skew_evd_opts *opts);
+
+/* Create a handle bound to the current HIP device and to the HIP stream
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  The handle is not
+ * thread-safe; use one handle per host thread. */
+int skew_evd_create(skew_evd_handle *h, void *hip_stream);
+int skew_evd_destroy(skew_evd_handle h);
+
+/* The solver (Algorithm 1; Section 2.1 for the half spectrum).
+ *   n        order of A (n >= 0)
+ *   A        n x n, leading dimension lda >= max(1, n); strict lower triangle read
+ *   nev      number of eigenpairs, 0 <= nev <= ceil(n/2)
+ *   lambda   out, nev values: the nev smallest of the ceil(n/2) values
+ *            lambda >= 0 of the spectrum {+-i lambda} (plus the exact 0 of odd
+ *            n, returned as lambda[0] = 0), ascending
+ *   Z_re, Z_im  out, n x nev (leading dimensions ldzr, ldzi >= max(1, n)):
+ *            z_k = Z_re[:,k] + i Z_im[:,k] satisfies A z_k = +i lambda_k z_k,
+ *            ||z_k||_2 = 1, and the z_k are orthonormal.  conj(z_k) belongs to
+ *            -i lambda_k.  The phase of each z_k is unspecified.
+ *   opts     NULL = defaults
+ *   info     NULL or filled after the call's device work completed
+ * skew_evd_ex is synchronous with respect to the handle's stream: it returns
+ * after the results are in Z_re/Z_im/lambda.  Argument numbers for errors:
+ * -2 n, -3 A, -4 lda, -5 nev, -6 lambda, -7 Z_re, -8 ldzr, -9 Z_im, -10 ldzi,
+ * -11 opts. */
+int skew_evd_ex(skew_evd_handle h, int n, const double *A, int lda, int nev,
+                double *lambda, double *Z_re, int ldzr, double *Z_im, int ldzi,
+                const skew_evd_opts *opts, skew_evd_info *info);
+
+/* Convenience form with ldz = n, default options, an internal handle on the
+ * null stream of the current device.  Errors: -1 n, -2 A, -3 lda, -4 nev,
+ * -5 lambda, -6 Z_re, -7 Z_im. */
+int skew_evd(int n, const double *A, int lda, int nev,
+             double *lambda, double *Z_re, double *Z_im);
+
+/* Batched form: count independent problems (host arrays of per-problem sizes
+ * and device pointers), each solved as by skew_evd_ex with ldz = n[i].
+ * status[i] (host) receives each problem's status; the return value is the
+ * first non-zero status (or a negative argument error: -2 count, -3 n,
+ * -4 A, -5 lda, -6 nev, -7 lambda, -8 Z_re, -9 Z_im, -12 status). */
+int skew_evd_batched(skew_evd_handle h, int count, const int *n,
+                     const double *const *A, const int *lda, const int *nev,
+                     double *const *lambda, double *const *Z_re,
+                     double *const *Z_im, const skew_evd_opts *opts,
+                     skew_evd_info *info, int *status);
+
+/* Stage entry points (building blocks, also used by the stage-level tests). */
+
+/* Full-to-band reduction (Section 2.3.2): B = Q_band^T A Q_band with semi-
+ * bandwidth b.  band: (b+1) x n column-major, ldband >= b+1, LAPACK lower band
+ * storage: band[d + j*ldband] = B[j+d, j], d = 0..b (the diagonal row d = 0 is
+ * written as 0).  Errors: -2 n, -3 A, -4 lda, -5 b, -6 band, -7 ldband. */
+int skew_evd_band_reduce(skew_evd_handle h, int n, const double *A, int lda,
+                         int b, double *band, int ldband);
+
+/* Two-stage tridiagonalization (Algorithm 1, step 1): alpha[j] = A_trd[j, j+1],
+ * j = 0..n-2 (the super-diagonal; the sub-diagonal is -alpha).
+ * Errors: -2 n, -3 A, -4 lda, -5 b, -6 alpha. */
+int skew_evd_tridiagonalize(skew_evd_handle h, int n, const double *A, int lda,
+                            int b, double *alpha);
+
+/* Symmetric tridiagonal eigensolve (Algorithm 1, step 2, Lemma 1):
+ * T = tridiag(alpha, 0, alpha) of order n; lambda[0..nev) = its eigenvalues
+ * with ascending indices floor(n/2)..floor(n/2)+nev-1 (the non-negative half),
+ * Q (n x nev, ldq >= n) the orthonormal eigenvectors.
+ * Errors: -2 n, -3 alpha, -4 nev, -5 lambda, -6 Q, -7 ldq. */
+int skew_evd_tridiag_eig(skew_evd_handle h, int n, const double *alpha, int nev,
+                         double *lambda, double *Q, int ldq);
+
+/* Text for a status code (static storage; for SKEW_EVD_ERR_HIP the text of the
+ * most recent HIP error seen by this thread). */
+const char *skew_evd_status_string(int status);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int skew_evd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKEW_EVD_H */

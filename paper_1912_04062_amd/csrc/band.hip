@@ -1,0 +1,481 @@
+// Full-to-band reduction of a skew-symmetric matrix (Section 2.3.2: blocked
+// Householder reduction with the compact WY form Q = I - V T V^T, and the
+// skew two-sided update A <- Q^T A Q = A + V W^T - W V^T).
+//
+// For a panel with reflectors V (m x b) and T (b x b), with A the trailing
+// skew block:  Y = A V T,  X = T^T V^T Y (b x b, skew),  W = Y - V X / 2, and
+// then  A <- A + V W^T - W V^T.  (Derivation: V^T A = -(A V)^T for skew A, so
+// the update of the paper's Eq. for ELPA2, A + [V U2][U1 V]^T, has U2 = -U1
+// = -W.)  Only the strict lower triangle of A is stored and updated.
+//
+// Kernels:
+//   k_ingest      copy the strict lower triangle of A into the work matrix,
+//                 flagging non-finite entries
+//   k_panel_qr    Householder QR of one panel, cooperative (grid barriers),
+//                 rows resident in LDS, FP64 norms and dot products; also
+//                 accumulates T column by column
+//   k_skew_symm   Y0 = A V (split-K partials), A read from the lower triangle
+//                 in both orientations
+//   k_ysum        Y0 = sum of the split-K partials
+//   k_gram        partial V^T Y0
+//   k_small       X = T^T (V^T Y0) T and the 2b x b matrix [T; -X/2]
+//   k_wform       W = [Y0 V] [T; -X/2]
+//   k_skew_syr2k  lower tiles A += [V W][W -V]^T
+//   k_band_extract  lower band storage of the result
+#include "common.h"
+#include "gemm.h"
+#include "kernels.h"
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ingest(const double *__restrict__ A, int lda, int n,
+                                                T *__restrict__ W, int ldw, unsigned *flags)
+{
+    const int j = blockIdx.y;
+    bool bad = false;
+    for (int i = j + 1 + blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        double a = A[(size_t)j * lda + i];
+        if (!__builtin_isfinite(a)) bad = true;
+        W[(size_t)j * ldw + i] = (T)a;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) W[(size_t)j * ldw + j] = T(0);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&flags[0], 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Panel QR.  ROWS rows per workgroup, 256 threads; the workgroup's rows live
+// in LDS as P[g][0..B) (double).  Column l:
+//   partial sums  s_t = sum_{g>l} P[g][l] P[g][t] (t >= l; t = l gives the
+//   squared norm below the diagonal) and z_t = sum_{g>=l} P[g][t] P[g][l-1]
+//   (t < l-1; dot products of the previous reflector with the earlier ones,
+//   for T), one grid barrier, then every workgroup reduces the partials in
+//   the same order (bitwise-identical scalars everywhere) and updates its rows.
+// Row l (l < B <= ROWS) always lives in workgroup 0, which broadcasts it.
+constexpr int PQR_ROWS = 128;
+
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_panel_qr(T *__restrict__ W, int ldw, int c0, int r0, int m,
+                                                  T *__restrict__ Vd, double *__restrict__ tau,
+                                                  double *__restrict__ Tf, double *__restrict__ part,
+                                                  unsigned *bar, unsigned bar_base, unsigned *err)
+{
+    extern __shared__ double sm[];
+    double *P = sm;                        // [ROWS][B]
+    double *Ts = sm + PQR_ROWS * B;        // [B][B] column-major (workgroup 0 only)
+    __shared__ double red[256];
+    __shared__ double tot[B], piv[B], ppiv[B], wv[B], vtmp[PQR_ROWS];
+    __shared__ double sc[4];               // tau, beta, scale, previous tau
+    constexpr int NP = 256 / B;            // parts
+    constexpr int RP = PQR_ROWS / NP;      // rows per part
+    const int tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
+    const int tcol = tid % B, tp = tid / B;
+    const int gbase = wg * PQR_ROWS;
+    const int L = m < B ? m : B;           // columns that get a reflector
+    double *pbuf = part;                   // [2][G][B]
+    double *pvbuf = part + 2 * (size_t)G * B;  // [2][B]
+
+    for (int e = tid; e < PQR_ROWS * B; e += 256) {
+        int g = e / B, t = e % B;
+        int gg = gbase + g;
+        P[e] = (gg < m) ? (double)W[(size_t)(c0 + t) * ldw + r0 + gg] : 0.0;
+    }
+    if (wg == 0)
+        for (int e = tid; e < B * B; e += 256) Ts[e] = 0.0;
+    __syncthreads();
+
+    unsigned nbar = 0;
+    for (int l = 0; l <= L; ++l) {
+        // ---- partial sums
+        double val = 0.0;
+        const int lm1 = l - 1;
+        for (int r = 0; r < RP; ++r) {
+            int g = tp * RP + r, gg = gbase + g;
+            if (gg >= m) break;
+            if (l < L && tcol >= l && gg > l) val += P[g * B + l] * P[g * B + tcol];
+            if (tcol < lm1 && gg >= l) val += P[g * B + tcol] * P[g * B + lm1];
+        }
+        red[tid] = val;
+        __syncthreads();
+        const int par = l & 1;
+        if (tid < B) {
+            double s = 0.0;
+            for (int p = 0; p < NP; ++p) s += red[p * B + tid];
+            pbuf[((size_t)par * G + wg) * B + tid] = s;
+            if (wg == 0) pvbuf[par * B + tid] = (l < L) ? P[l * B + tid] : 0.0;
+        }
+        ++nbar;
+        if (!grid_sync(bar, bar_base + nbar * G, err)) return;
+        if (tid < B) {
+            double s = 0.0;
+            for (int w = 0; w < G; ++w) s += pbuf[((size_t)par * G + w) * B + tid];
+            tot[tid] = s;
+            piv[tid] = pvbuf[par * B + tid];
+        }
+        __syncthreads();
+        // ---- T column l-1: T[0:l-1, l-1] = -tau_{l-1} T[0:l-1, 0:l-1] z
+        if (wg == 0 && l >= 1) {
+            const double tprev = sc[3];
+            if (tid < lm1) {
+                double s = 0.0;
+                for (int u = tid; u < lm1; ++u) s += Ts[u * B + tid] * (tot[u] + ppiv[u]);
+                red[tid] = -tprev * s;
+            }
+            __syncthreads();
+            if (tid < lm1) Ts[lm1 * B + tid] = red[tid];
+            if (tid == 0) Ts[lm1 * B + lm1] = tprev;
+            __syncthreads();
+        }
+        if (l == L) break;
+        // ---- reflector of column l (every workgroup, same arithmetic)
+        if (tid == 0) {
+            double x0 = piv[l], ss = tot[l];
+            double t = 0.0, beta = x0, scale = 0.0;
+            if (ss != 0.0) {
+                double nrm = sqrt(x0 * x0 + ss);
+                beta = (x0 >= 0.0) ? -nrm : nrm;
+                t = (beta - x0) / beta;
+                scale = 1.0 / (x0 - beta);
+            }
+            sc[0] = t; sc[1] = beta; sc[2] = scale;
+        }
+        __syncthreads();
+        const double t = sc[0], beta = sc[1], scale = sc[2];
+        if (tid < B) wv[tid] = (tid > l) ? t * (piv[tid] + scale * tot[tid]) : 0.0;
+        if (tid < PQR_ROWS) {
+            int gg = gbase + tid;
+            vtmp[tid] = (gg > l && gg < m) ? P[tid * B + l] * scale : (gg == l ? 1.0 : 0.0);
+        }
+        if (tid < B) ppiv[tid] = piv[tid];
+        __syncthreads();
+        for (int r = 0; r < RP; ++r) {
+            int g = tp * RP + r, gg = gbase + g;
+            if (gg >= m) break;
+            if (gg < l) continue;
+            if (tcol > l) P[g * B + tcol] -= vtmp[g] * wv[tcol];
+            else if (tcol == l) P[g * B + l] = (gg == l) ? beta : vtmp[g];
+        }
+        if (tid == 0) {
+            sc[3] = t;
+            if (wg == 0) tau[l] = t;
+        }
+        __syncthreads();
+    }
+    // columns without a reflector
+    if (wg == 0 && tid >= L && tid < B) tau[tid] = 0.0;
+    // ---- write back: R and V into the panel, dense V, T
+    for (int e = tid; e < PQR_ROWS * B; e += 256) {
+        int g = e % PQR_ROWS, t = e / PQR_ROWS;
+        int gg = gbase + g;
+        if (gg < m) {
+            double p = P[g * B + t];
+            W[(size_t)(c0 + t) * ldw + r0 + gg] = (T)p;
+            double v = (gg > t) ? p : ((gg == t && t < L) ? 1.0 : 0.0);
+            Vd[(size_t)t * m + gg] = (T)v;
+        }
+    }
+    if (wg == 0)
+        for (int e = tid; e < B * B; e += 256) Tf[e] = Ts[e];
+}
+
+// ---------------------------------------------------------------------------
+// Y0 partial (split s): rows [m0, m0+64) of  A_trail V  over k in [kb, ke).
+template <typename T, int TN>
+__global__ __launch_bounds__(256) void k_skew_symm(const T *__restrict__ W, int ldw, int r0, int m,
+                                                   const T *__restrict__ Vd, int B,
+                                                   T *__restrict__ Ypart, int kchunk)
+{
+    constexpr int TM = 64;
+    extern __shared__ char smraw[];
+    T *smem = (T *)smraw;
+    const int m0 = blockIdx.x * TM;
+    const int s = blockIdx.y;
+    const int kb = s * kchunk, ke = min(m, kb + kchunk);
+    const T *A0 = W + (size_t)r0 * ldw + r0;
+    auto f_low = [=](int i, int k) -> T {      // k < i
+        return (i < m && k < ke) ? A0[(size_t)k * ldw + i] : T(0);
+    };
+    auto f_up = [=](int i, int k) -> T {       // k > i: A(i,k) = -A(k,i)
+        return (i < m && k < ke) ? -A0[(size_t)i * ldw + k] : T(0);
+    };
+    auto f_mix = [=](int i, int k) -> T {
+        if (i >= m || k >= ke || i == k) return T(0);
+        return (i > k) ? A0[(size_t)k * ldw + i] : -A0[(size_t)i * ldw + k];
+    };
+    auto f_v = [=](int j, int k) -> T {
+        return (j < B && k < ke) ? Vd[(size_t)j * m + k] : T(0);
+    };
+    gemm::Acc<T, TM, TN> acc;
+    acc.zero();
+    T *As = smem, *Bs = smem + gemm::TK * (TM + 1);
+    for (int k0 = kb; k0 < ke; k0 += gemm::TK) {
+        if (k0 + gemm::TK <= m0) gemm::fill<T, TM, false>(As, f_low, m0, k0);
+        else if (k0 >= m0 + TM) gemm::fill<T, TM, true>(As, f_up, m0, k0);
+        else gemm::fill<T, TM, false>(As, f_mix, m0, k0);
+        gemm::fill<T, TN, true>(Bs, f_v, 0, k0);
+        __syncthreads();
+        gemm::mma_chunk<T, TM, TN>(As, Bs, acc);
+        __syncthreads();
+    }
+    T *Y = Ypart + (size_t)s * m * B;
+    gemm::epilogue<T, TM, TN>(acc, [=](int i, int j, T v) {
+        if (m0 + i < m && j < B) Y[(size_t)j * m + m0 + i] = v;
+    });
+}
+
+template <typename T>
+__global__ void k_ysum(const T *__restrict__ Ypart, int S, size_t len, T *__restrict__ Y0)
+{
+    for (size_t e = blockIdx.x * (size_t)256 + threadIdx.x; e < len; e += (size_t)gridDim.x * 256) {
+        double s = 0.0;
+        for (int p = 0; p < S; ++p) s += (double)Ypart[(size_t)p * len + e];
+        Y0[e] = (T)s;
+    }
+}
+
+// Partial V^T Y0 over row chunk blockIdx.x (rows [c*rc, (c+1)*rc)).
+template <typename T, int TB>
+__global__ __launch_bounds__(256) void k_gram(const T *__restrict__ Vd, const T *__restrict__ Y0,
+                                              int m, int B, int rc, double *__restrict__ Gp)
+{
+    extern __shared__ char smraw[];
+    T *smem = (T *)smraw;
+    const int kb = blockIdx.x * rc, ke = min(m, kb + rc);
+    auto fa = [=](int l, int g) -> T { return (l < B && g < ke) ? Vd[(size_t)l * m + g] : T(0); };
+    auto fb = [=](int j, int g) -> T { return (j < B && g < ke) ? Y0[(size_t)j * m + g] : T(0); };
+    gemm::Acc<T, TB, TB> acc;
+    acc.zero();
+    gemm::kloop<T, TB, TB, true, true>(fa, fb, 0, 0, kb, ke, smem, acc);
+    double *G = Gp + (size_t)blockIdx.x * B * B;
+    gemm::epilogue<T, TB, TB>(acc, [=](int i, int j, T v) {
+        if (i < B && j < B) G[(size_t)j * B + i] = (double)v;
+    });
+}
+
+// X = T^T G T with G = sum of the chunk partials; Tx = [T; -X/2] (2B x B).
+template <typename T>
+__global__ __launch_bounds__(256) void k_small(const double *__restrict__ Gp, int nchunk, int B,
+                                               const double *__restrict__ Tf, T *__restrict__ Tx)
+{
+    __shared__ double G[64 * 64], Tm[64 * 64], M1[64 * 64];
+    const int tid = threadIdx.x, BB = B * B;
+    for (int e = tid; e < BB; e += 256) {
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c) s += Gp[(size_t)c * BB + e];
+        G[e] = s;
+        Tm[e] = Tf[e];
+    }
+    __syncthreads();
+    for (int e = tid; e < BB; e += 256) {       // M1 = G T
+        int i = e % B, j = e / B;
+        double s = 0.0;
+        for (int u = 0; u <= j; ++u) s += G[u * B + i] * Tm[j * B + u];
+        M1[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < BB; e += 256) {       // X = T^T M1
+        int i = e % B, j = e / B;
+        double s = 0.0;
+        for (int u = 0; u <= i; ++u) s += Tm[i * B + u] * M1[j * B + u];
+        Tx[(size_t)j * 2 * B + i] = (T)Tm[e];
+        Tx[(size_t)j * 2 * B + B + i] = (T)(-0.5 * s);
+    }
+}
+
+// W = [Y0 V] Tx  (m x B)
+template <typename T, int TN>
+__global__ __launch_bounds__(256) void k_wform(const T *__restrict__ Y0, const T *__restrict__ Vd,
+                                               const T *__restrict__ Tx, int m, int B,
+                                               T *__restrict__ Wd)
+{
+    constexpr int TM = 64;
+    extern __shared__ char smraw[];
+    T *smem = (T *)smraw;
+    const int m0 = blockIdx.x * TM;
+    auto fa = [=](int i, int k) -> T {
+        if (i >= m || k >= 2 * B) return T(0);
+        return k < B ? Y0[(size_t)k * m + i] : Vd[(size_t)(k - B) * m + i];
+    };
+    auto fb = [=](int j, int k) -> T { return (j < B && k < 2 * B) ? Tx[(size_t)j * 2 * B + k] : T(0); };
+    gemm::Acc<T, TM, TN> acc;
+    acc.zero();
+    gemm::kloop<T, TM, TN, false, true>(fa, fb, m0, 0, 0, 2 * B, smem, acc);
+    gemm::epilogue<T, TM, TN>(acc, [=](int i, int j, T v) {
+        if (m0 + i < m && j < B) Wd[(size_t)j * m + m0 + i] = v;
+    });
+}
+
+// Lower tiles (I >= J) of the trailing block: A += V W^T - W V^T.
+__device__ __forceinline__ void tri_index(int t, int &I, int &J)
+{
+    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
+template <typename T, int TT>
+__global__ __launch_bounds__(256) void k_skew_syr2k(T *__restrict__ W, int ldw, int r0, int m,
+                                                    const T *__restrict__ Vd, const T *__restrict__ Wd,
+                                                    int B)
+{
+    extern __shared__ char smraw[];
+    T *smem = (T *)smraw;
+    int I, J;
+    tri_index(blockIdx.x, I, J);
+    const int m0 = I * TT, n0 = J * TT;
+    auto fa = [=](int i, int k) -> T {
+        if (i >= m) return T(0);
+        return k < B ? Vd[(size_t)k * m + i] : Wd[(size_t)(k - B) * m + i];
+    };
+    auto fb = [=](int j, int k) -> T {
+        if (j >= m) return T(0);
+        return k < B ? Wd[(size_t)k * m + j] : -Vd[(size_t)(k - B) * m + j];
+    };
+    gemm::Acc<T, TT, TT> acc;
+    acc.zero();
+    gemm::kloop<T, TT, TT, false, false>(fa, fb, m0, n0, 0, 2 * B, smem, acc);
+    T *A0 = W + (size_t)r0 * ldw + r0;
+    const bool diag = (I == J);
+    gemm::epilogue<T, TT, TT>(acc, [=](int i, int j, T v) {
+        int gi = m0 + i, gj = n0 + j;
+        if (gi < m && gj < m && (!diag || i > j)) A0[(size_t)gj * ldw + gi] += v;
+    });
+}
+
+template <typename T>
+__global__ void k_band_extract(const T *__restrict__ W, int ldw, int n, int b,
+                               double *__restrict__ ab, int ldab)
+{
+    const int j = blockIdx.x * blockDim.y + threadIdx.y;
+    if (j >= n) return;
+    for (int d = threadIdx.x; d < ldab; d += blockDim.x) {
+        double v = 0.0;
+        if (d >= 1 && d <= b && j + d < n) v = (double)W[(size_t)j * ldw + j + d];
+        ab[(size_t)j * ldab + d] = v;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host launchers
+namespace skew {
+
+template <typename T>
+void launch_ingest(const double *A, int lda, int n, T *W, int ldw, unsigned *flags, hipStream_t st)
+{
+    if (n <= 0) return;
+    dim3 grid(cdiv(n, 256) > 16 ? 16 : cdiv(n, 256), n);
+    hipLaunchKernelGGL(k_ingest<T>, grid, dim3(256), 0, st, A, lda, n, W, ldw, flags);
+}
+
+int panel_qr_groups(int m) { return (int)cdiv(m, PQR_ROWS); }
+size_t panel_qr_part_doubles(int m, int B) { return 2 * (size_t)panel_qr_groups(m) * B + 2 * B; }
+
+template <typename T, int B>
+static hipError_t panel_qr_b(T *W, int ldw, int c0, int r0, int m, T *Vd, double *tau, double *Tf,
+                             double *part, unsigned *bar, unsigned bar_base, unsigned *err,
+                             hipStream_t st)
+{
+    const int G = panel_qr_groups(m);
+    size_t shm = sizeof(double) * ((size_t)PQR_ROWS * B + (size_t)B * B);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_panel_qr<T, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shm);
+        attr = true;
+    }
+    void *args[] = {&W, &ldw, &c0, &r0, &m, &Vd, &tau, &Tf, &part, &bar, &bar_base, &err};
+    return hipLaunchCooperativeKernel((const void *)k_panel_qr<T, B>, dim3(G), dim3(256), args, shm, st);
+}
+
+template <typename T>
+hipError_t launch_panel_qr(T *W, int ldw, int c0, int r0, int m, int B, T *Vd, double *tau, double *Tf,
+                           double *part, unsigned *bar, unsigned bar_base, unsigned *err, hipStream_t st)
+{
+    switch (B) {
+    case 8: return panel_qr_b<T, 8>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, st);
+    case 16: return panel_qr_b<T, 16>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, st);
+    case 32: return panel_qr_b<T, 32>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, st);
+    case 64: return panel_qr_b<T, 64>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int symm_splits(int m)
+{
+    int rows = (int)cdiv(m, 64);
+    int S = (int)cdiv(1024, rows > 0 ? rows : 1);
+    int maxS = (int)cdiv(m, 256);
+    if (S > maxS) S = maxS;
+    if (S > 16) S = 16;
+    if (S < 1) S = 1;
+    return S;
+}
+int symm_kchunk(int m, int S) { return (int)(cdiv(cdiv(m, S), 16) * 16); }
+int gram_chunk_rows() { return 512; }
+
+template <typename T>
+void launch_stage1_update(T *W, int ldw, int r0, int m, int B, const T *Vd, const double *Tf, T *Ypart,
+                          T *Y0, T *Wd, double *Gp, T *Tx, hipStream_t st)
+{
+    const int S = symm_splits(m);
+    const int kc = symm_kchunk(m, S);
+    const int S_eff = (int)cdiv(m, kc);
+    dim3 g1(cdiv(m, 64), S_eff);
+    if (B > 32) {
+        hipLaunchKernelGGL((k_skew_symm<T, 64>), g1, dim3(256), (gemm::smem_bytes<T, 64, 64>()), st,
+                           (const T *)W, ldw, r0, m, Vd, B, Ypart, kc);
+    } else {
+        hipLaunchKernelGGL((k_skew_symm<T, 32>), g1, dim3(256), (gemm::smem_bytes<T, 64, 32>()), st,
+                           (const T *)W, ldw, r0, m, Vd, B, Ypart, kc);
+    }
+    size_t len = (size_t)m * B;
+    hipLaunchKernelGGL(k_ysum<T>, dim3(cdiv(len, 256) > 2048 ? 2048 : cdiv(len, 256)), dim3(256), 0, st,
+                       (const T *)Ypart, S_eff, len, Y0);
+    const int rc = gram_chunk_rows();
+    const int nch = (int)cdiv(m, rc);
+    if (B > 32)
+        hipLaunchKernelGGL((k_gram<T, 64>), dim3(nch), dim3(256), (gemm::smem_bytes<T, 64, 64>()), st,
+                           (const T *)Vd, (const T *)Y0, m, B, rc, Gp);
+    else
+        hipLaunchKernelGGL((k_gram<T, 32>), dim3(nch), dim3(256), (gemm::smem_bytes<T, 32, 32>()), st,
+                           (const T *)Vd, (const T *)Y0, m, B, rc, Gp);
+    hipLaunchKernelGGL(k_small<T>, dim3(1), dim3(256), 0, st, (const double *)Gp, nch, B, Tf, Tx);
+    if (B > 32)
+        hipLaunchKernelGGL((k_wform<T, 64>), dim3(cdiv(m, 64)), dim3(256), (gemm::smem_bytes<T, 64, 64>()), st,
+                           (const T *)Y0, Vd, (const T *)Tx, m, B, Wd);
+    else
+        hipLaunchKernelGGL((k_wform<T, 32>), dim3(cdiv(m, 64)), dim3(256), (gemm::smem_bytes<T, 64, 32>()), st,
+                           (const T *)Y0, Vd, (const T *)Tx, m, B, Wd);
+    const int TT = 64;
+    unsigned nt = cdiv(m, TT);
+    unsigned ntiles = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL((k_skew_syr2k<T, 64>), dim3(ntiles), dim3(256), (gemm::smem_bytes<T, 64, 64>()), st,
+                       W, ldw, r0, m, Vd, (const T *)Wd, B);
+}
+
+template <typename T>
+void launch_band_extract(const T *W, int ldw, int n, int b, double *ab, int ldab, hipStream_t st)
+{
+    if (n <= 0) return;
+    dim3 blk(64, 4);
+    hipLaunchKernelGGL(k_band_extract<T>, dim3(cdiv(n, 4)), blk, 0, st, W, ldw, n, b, ab, ldab);
+}
+
+template void launch_ingest<double>(const double *, int, int, double *, int, unsigned *, hipStream_t);
+template void launch_ingest<float>(const double *, int, int, float *, int, unsigned *, hipStream_t);
+template hipError_t launch_panel_qr<double>(double *, int, int, int, int, int, double *, double *, double *,
+                                            double *, unsigned *, unsigned, unsigned *, hipStream_t);
+template hipError_t launch_panel_qr<float>(float *, int, int, int, int, int, float *, double *, double *,
+                                           double *, unsigned *, unsigned, unsigned *, hipStream_t);
+template void launch_stage1_update<double>(double *, int, int, int, int, const double *, const double *,
+                                           double *, double *, double *, double *, double *, hipStream_t);
+template void launch_stage1_update<float>(float *, int, int, int, int, const float *, const double *,
+                                          float *, float *, float *, double *, float *, hipStream_t);
+template void launch_band_extract<double>(const double *, int, int, int, double *, int, hipStream_t);
+template void launch_band_extract<float>(const float *, int, int, int, double *, int, hipStream_t);
+
+}  // namespace skew

@@ -1,0 +1,84 @@
+// Internal helpers shared by the HIP kernels of the skew-symmetric eigensolver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Accumulator vector type of the 16x16x4 MFMA for an element type.
+template <typename T> struct acc4;
+template <> struct acc4<double> { typedef d4 type; };
+template <> struct acc4<float> { typedef f4 type; };
+
+// D = A*B + C on a 16x16 tile with K = 4 (one wavefront).  Lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; it receives D[row][l%16] in its r-th
+// result register (r = 0..3) with row = mfma_row<T>(l, r): l/16 + 4r for the
+// FP64 instruction and 4(l/16) + r for the FP32 one (measured on gfx950).
+template <typename T> __device__ __forceinline__ int mfma_row(int lane, int r);
+template <> __device__ __forceinline__ int mfma_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+template <> __device__ __forceinline__ int mfma_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+__device__ __forceinline__ d4 mfma_16x16x4(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_16x16x4(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Bounded spin for device-side waits: a wait that exceeds it sets the error
+// word and gives up, so every wave of a persistent kernel always exits.
+#define SKEW_SPIN_LIMIT (1u << 22)
+
+// Agent-scope acquire/release accessors for flags and counters.
+__device__ __forceinline__ unsigned ld_acquire(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(unsigned *p, unsigned v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_release(unsigned *p, unsigned v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier for cooperatively launched kernels: a monotonic counter
+// that every workgroup increments once per barrier; `target` is the count at
+// which this barrier opens.  Returns false when the wait gave up.
+__device__ __forceinline__ bool grid_sync(unsigned *ctr, unsigned target, unsigned *err)
+{
+    __shared__ int gs_ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        add_release(ctr, 1u);
+        unsigned spins = 0;
+        int ok = 1;
+        while (ld_acquire(ctr) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > SKEW_SPIN_LIMIT) {
+                atomicOr(err, 1u);
+                ok = 0;
+                break;
+            }
+        }
+        gs_ok = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return gs_ok != 0;
+}
+
+// Wavefront sum (64 lanes) via cross-lane shuffles.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+static inline unsigned cdiv(unsigned a, unsigned b) { return (a + b - 1) / b; }

@@ -1,0 +1,59 @@
+// Host-side launchers of the device kernels (internal interface between the
+// stage drivers in api.cpp and the kernel files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace skew {
+
+// band.hip
+template <typename T>
+void launch_ingest(const double *A, int lda, int n, T *W, int ldw, unsigned *flags, hipStream_t st);
+int panel_qr_groups(int m);
+size_t panel_qr_part_doubles(int m, int B);
+template <typename T>
+hipError_t launch_panel_qr(T *W, int ldw, int c0, int r0, int m, int B, T *Vd, double *tau, double *Tf,
+                           double *part, unsigned *bar, unsigned bar_base, unsigned *err, hipStream_t st);
+int symm_splits(int m);
+int symm_kchunk(int m, int S);
+int gram_chunk_rows();
+template <typename T>
+void launch_stage1_update(T *W, int ldw, int r0, int m, int B, const T *Vd, const double *Tf, T *Ypart,
+                          T *Y0, T *Wd, double *Gp, T *Tx, hipStream_t st);
+template <typename T>
+void launch_band_extract(const T *W, int ldw, int n, int b, double *ab, int ldab, hipStream_t st);
+
+// chase.hip
+int chase_ngroups(int n, int b, int nb2, int *goff_host);
+hipError_t launch_chase(double *ab, int ldab, int n, int b, int nb2, double *V2, double *tau2,
+                        const int *goff, unsigned *progress, unsigned *err, double *alpha, hipStream_t st);
+
+// tridiag.hip
+void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, double *a2, double *stats,
+                            double *w, hipStream_t st);
+void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
+                            double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
+                            double *Q, int ldq, hipStream_t st);
+void launch_chol_inv(const double *Gp, int nparts, int NB, double *Rinv, hipStream_t st);
+
+// backtransform.hip
+template <typename T>
+void launch_dscale(const double *Q, int ldq, int n, int nev, T *Z, int ldz, hipStream_t st);
+template <typename T>
+void launch_bt2(T *Z, int ldz, int n, int ncols, int b, int nb2, const double *V2, const double *tau2, T *T2,
+                T *V2t, const int *goff_dev, int nsig, int ngroups, hipStream_t st);
+int tn_splits(int K, int tiles);
+template <typename T>
+int launch_gemm_tn_part(const T *A, int lda, const T *B, int ldb, int M, int N, int K, double *Cpart,
+                        hipStream_t st);
+template <typename T>
+void launch_gemm_nn(const T *A, int lda, const double *Bpart, int S, int M, int N, int K, T *C, int ldc,
+                    double alpha, int beta, hipStream_t st);
+void launch_reduce_left(const double *S0, const double *Cpart, int S, int M, int N, double *out,
+                        hipStream_t st);
+template <typename T>
+void launch_copy_cols(const T *src, int lds, T *dst, int ldd, int m, int ncol, hipStream_t st);
+template <typename T>
+void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int ncol, hipStream_t st);
+
+}  // namespace skew

@@ -1,0 +1,330 @@
+// Symmetric tridiagonal eigensolver for T = tridiag(alpha, 0, alpha)
+// (Algorithm 1, step 2; Lemma 1 turns the skew tridiagonal into this matrix,
+// whose off-diagonal is the super-diagonal alpha of the skew one).
+//
+//   k_bisect   eigenvalues by Sturm-sequence multisection: 16 lanes evaluate
+//              the inertia count at 16 interior points of the current
+//              interval, which shrinks 17-fold per round (4 bits).  The
+//              counts use d_i = -x - alpha_{i-1}^2 / d_{i-1} with tiny pivots
+//              replaced by -pivmin.  alpha^2 is staged through LDS in chunks.
+//   k_invit    eigenvectors by inverse iteration, one thread per vector, on
+//              T - lambda I factored by Gaussian elimination with partial
+//              pivoting (U gets a second super-diagonal); factors and
+//              iterates live in [i][k] layout so that consecutive vectors are
+//              consecutive in memory.  For lambda > 0 the even- and odd-
+//              indexed halves of an exact eigenvector have equal norms, so
+//              each half is scaled to 1/sqrt(2).
+//   k_nullvec  for odd n the exact zero eigenvalue's vector from the two-term
+//              recurrence of T q = 0 (odd entries zero), when it applies.
+// Orthogonality across close eigenvalues is restored afterwards by a block
+// Gram-Schmidt pass in eigenvalue order (host code, using the GEMM kernels).
+#include "common.h"
+#include "gemm.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int BIS_NS = 16;       // shifts per eigenvalue
+constexpr int BIS_CH = 2048;     // alpha^2 chunk staged in LDS
+
+__global__ void k_alpha2(const double *__restrict__ alpha, int n, double *__restrict__ a2,
+                         double *__restrict__ stats)
+{
+    // a2[i] = alpha[i]^2 (i < n-1); stats[0] = ||T||_inf, stats[1] = max alpha^2
+    __shared__ double mx[256], mg[256];
+    double lm = 0.0, lg = 0.0;
+    for (int i = threadIdx.x; i < n - 1; i += 256) {
+        double a = alpha[i];
+        a2[i] = a * a;
+        lm = fmax(lm, a * a);
+        double r = fabs(a) + ((i + 1 < n - 1) ? fabs(alpha[i + 1]) : 0.0);
+        lg = fmax(lg, r);
+        if (i == 0) lg = fmax(lg, fabs(a));
+    }
+    mx[threadIdx.x] = lm;
+    mg[threadIdx.x] = lg;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
+            mg[threadIdx.x] = fmax(mg[threadIdx.x], mg[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stats[0] = mg[0];
+        stats[1] = mx[0];
+    }
+}
+
+// 256 threads = 16 eigenvalues x 16 shifts.  Eigenvalue index first + e.
+__global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, int n, int first, int count,
+                                                const double *__restrict__ stats, int rounds,
+                                                double *__restrict__ w)
+{
+    __shared__ double sa[BIS_CH];
+    const int q = threadIdx.x & (BIS_NS - 1);
+    const int e = blockIdx.x * (256 / BIS_NS) + threadIdx.x / BIS_NS;
+    const bool active = e < count;
+    const int idx = first + (active ? e : 0);
+    const double g = stats[0];
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, stats[1]);
+    const double eps = 2.220446049250313e-16;
+    double lo = -g * (1.0 + 2.0 * eps) - 2.0 * pivmin;
+    double hi = g * (1.0 + 2.0 * eps) + 2.0 * pivmin;
+    for (int r = 0; r < rounds; ++r) {
+        const double h = (hi - lo) / (BIS_NS + 1);
+        const double xq = lo + (q + 1) * h;
+        double d = -xq;
+        if (fabs(d) < pivmin) d = -pivmin;
+        int cnt = (d < 0.0) ? 1 : 0;
+        for (int c0 = 0; c0 < n - 1; c0 += BIS_CH) {
+            const int len = min(BIS_CH, n - 1 - c0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < len; i += 256) sa[i] = a2[c0 + i];
+            __syncthreads();
+            for (int i = 0; i < len; ++i) {
+                d = -xq - sa[i] / d;
+                if (fabs(d) < pivmin) d = -pivmin;
+                cnt += (d < 0.0) ? 1 : 0;
+            }
+        }
+        // lanes with count <= idx have lambda_idx >= x_q
+        unsigned long long m = __ballot(cnt <= idx);
+        const int sh = (threadIdx.x & 63) & ~(BIS_NS - 1);
+        const int qs = __popcll((m >> sh) & ((1ull << BIS_NS) - 1));
+        const double nlo = (qs > 0) ? lo + qs * h : lo;
+        const double nhi = (qs < BIS_NS) ? lo + (qs + 1) * h : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (active && q == 0) {
+        double lam = 0.5 * (lo + hi);
+        if ((n & 1) && idx == n / 2) lam = 0.0;
+        w[e] = lam;
+    }
+}
+
+__device__ __forceinline__ double hash_uniform(unsigned long long seed, unsigned long long a, unsigned long long b)
+{
+    unsigned long long z = seed ^ (a * 0x9e3779b97f4a7c15ull) ^ (b * 0xc2b2ae3d27d4eb4full);
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+// One thread per vector.  Workspace (each n x nev, [i][k] layout):
+// U0, U1, U2 (rows of U), Lm (multipliers, negative zero never used as flag:
+// swaps kept in Sw), Y (iterate).
+__global__ __launch_bounds__(256) void k_invit(const double *__restrict__ alpha, int n, int nev,
+                                               const double *__restrict__ w,
+                                               const double *__restrict__ stats, int iters,
+                                               double *__restrict__ U0, double *__restrict__ U1,
+                                               double *__restrict__ U2, double *__restrict__ Lm,
+                                               unsigned char *__restrict__ Sw, double *__restrict__ Y)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= nev) return;
+    const size_t st = nev;
+    const double g = stats[0];
+    const double eps = 2.220446049250313e-16;
+    const double tiny = eps * (g > 0.0 ? g : 1.0);
+    const double lam = w[k];
+    // perturb coincident shifts apart (consecutive equal eigenvalues)
+    double shift = lam;
+    if (k > 0) {
+        int r = 0;
+        while (k - r - 1 >= 0 && w[k - r - 1] == lam && r < 64) ++r;
+        shift = lam + r * 10.0 * eps * fmax(fabs(lam), tiny);
+    }
+    // factor T - shift I
+    double a = -shift, bb = (n > 1) ? alpha[0] : 0.0, cc = 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+        const double sub = alpha[i], dn = -shift, en = (i + 2 < n) ? alpha[i + 1] : 0.0;
+        if (fabs(a) >= fabs(sub)) {
+            if (a == 0.0) a = tiny;
+            const double l = sub / a;
+            Sw[i * st + k] = 0;
+            Lm[i * st + k] = l;
+            U0[i * st + k] = a; U1[i * st + k] = bb; U2[i * st + k] = cc;
+            a = dn - l * bb; bb = en - l * cc; cc = 0.0;
+        } else {
+            const double l = a / sub;
+            Sw[i * st + k] = 1;
+            Lm[i * st + k] = l;
+            U0[i * st + k] = sub; U1[i * st + k] = dn; U2[i * st + k] = en;
+            a = bb - l * dn; bb = cc - l * en; cc = 0.0;
+        }
+    }
+    if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
+    U0[(size_t)(n - 1) * st + k] = a;
+    for (int i = 0; i + 1 < n; ++i) {
+        double u = U0[i * st + k];
+        if (fabs(u) < tiny) U0[i * st + k] = (u < 0.0) ? -tiny : tiny;
+    }
+    // start vector
+    for (int i = 0; i < n; ++i) Y[i * st + k] = hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i);
+    for (int it = 0; it < iters; ++it) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) { double yi = Y[i * st + k]; s += yi * yi; }
+        const double inv = 1.0 / sqrt(s);
+        // forward: P, L
+        double yprev = Y[k] * inv;
+        for (int i = 0; i + 1 < n; ++i) {
+            double ynext = Y[(i + 1) * st + k] * inv;
+            double yi = yprev;
+            if (Sw[i * st + k]) { double tt = yi; yi = ynext; ynext = tt; }
+            ynext -= Lm[i * st + k] * yi;
+            Y[i * st + k] = yi;
+            yprev = ynext;
+        }
+        Y[(size_t)(n - 1) * st + k] = yprev;
+        // backward: U
+        double x1 = 0.0, x2 = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+            double r = Y[i * st + k];
+            if (i + 1 < n) r -= U1[i * st + k] * x1;
+            if (i + 2 < n) r -= U2[i * st + k] * x2;
+            double xi = r / U0[i * st + k];
+            Y[i * st + k] = xi;
+            x2 = x1;
+            x1 = xi;
+        }
+    }
+    // normalise; for lambda > 0 the even and odd halves each to 1/sqrt(2)
+    double se = 0.0, so = 0.0;
+    for (int i = 0; i < n; i += 2) { double yi = Y[i * st + k]; se += yi * yi; }
+    for (int i = 1; i < n; i += 2) { double yi = Y[i * st + k]; so += yi * yi; }
+    double fe, fo;
+    if (lam > 0.0 && se > 0.0 && so > 0.0) {
+        fe = sqrt(0.5 / se);
+        fo = sqrt(0.5 / so);
+    } else {
+        fe = fo = 1.0 / sqrt(se + so);
+    }
+    for (int i = 0; i < n; ++i) Y[i * st + k] *= (i & 1) ? fo : fe;
+}
+
+// Odd n, lambda_0 = 0: q_0 = 1, q_{2m+2} = -alpha_{2m} q_{2m} / alpha_{2m+1},
+// odd entries 0; used only when every alpha_{2m+1} != 0 (else the inverse
+// iteration result stays).  Single thread; writes column 0 of Y ([i][k]).
+__global__ void k_nullvec(const double *__restrict__ alpha, int n, int nev, double *__restrict__ Y)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 1; i < n - 1; i += 2)
+        if (alpha[i] == 0.0) return;
+    const size_t st = nev;
+    double q = 1.0, s = 1.0;
+    Y[0] = 1.0;
+    for (int m2 = 0; m2 + 2 < n; m2 += 2) {
+        q = -alpha[m2] * q / alpha[m2 + 1];
+        if (fabs(q) > 1e150) {
+            for (int i = 0; i <= m2; i += 2) Y[i * st] *= 1e-150;
+            q *= 1e-150;
+            s *= 1e-300;
+        }
+        Y[(size_t)(m2 + 2) * st] = q;
+        s += q * q;
+    }
+    double ss = 0.0;
+    for (int i = 0; i < n; i += 2) ss += Y[i * st] * Y[i * st];
+    const double inv = 1.0 / sqrt(ss);
+    for (int i = 0; i < n; ++i) Y[i * st] = (i & 1) ? 0.0 : Y[i * st] * inv;
+}
+
+// Y ([i][k], n x nev) -> Q (column-major, ldq)
+__global__ void k_transpose(const double *__restrict__ Y, int n, int nev, double *__restrict__ Q, int ldq)
+{
+    __shared__ double tile[32][33];
+    const int k0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+    const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        int i = i0 + r, k = k0 + tx;
+        tile[r][tx] = (i < n && k < nev) ? Y[(size_t)i * nev + k] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        int k = k0 + r, i = i0 + tx;
+        if (i < n && k < nev) Q[(size_t)k * ldq + i] = tile[tx][r];
+    }
+}
+
+// Cholesky of G = sum of partials (NB x NB, NB <= 64) and R^{-1} (upper).
+__global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp, int nparts, int NB,
+                                                  double *__restrict__ Rinv)
+{
+    __shared__ double G[64 * 65], R[64 * 65];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += 256) {
+        double s = 0.0;
+        for (int p = 0; p < nparts; ++p) s += Gp[(size_t)p * NB * NB + e];
+        G[(e % NB) * 65 + e / NB] = s;      // G[i][j]
+    }
+    for (int e = tid; e < 64 * 65; e += 256) R[e] = 0.0;
+    __syncthreads();
+    // G = R^T R, R upper; column-by-column (right-looking on G)
+    for (int j = 0; j < NB; ++j) {
+        if (tid == 0) {
+            double d = G[j * 65 + j];
+            G[j * 65 + j] = sqrt(d > 0.0 ? d : 1e-300);
+        }
+        __syncthreads();
+        const double rjj = G[j * 65 + j];
+        if (tid > j && tid < NB) G[j * 65 + tid] /= rjj;      // row j of R
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += 256) {
+            int r = e / NB, c = e % NB;
+            if (r > j && c >= r) G[r * 65 + c] -= G[j * 65 + r] * G[j * 65 + c];
+        }
+        __syncthreads();
+    }
+    // invert the upper triangular R (row-major in G): column c of R^{-1}
+    if (tid < NB) {
+        const int c = tid;
+        for (int i = NB - 1; i >= 0; --i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int u = i + 1; u <= c; ++u) s -= G[i * 65 + u] * R[u * 65 + c];
+            R[i * 65 + c] = (i <= c) ? s / G[i * 65 + i] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+        int i = e % NB, j = e / NB;
+        Rinv[e] = R[i * 65 + j];          // column-major
+    }
+}
+
+}  // namespace
+
+namespace skew {
+
+void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, double *a2, double *stats,
+                            double *w, hipStream_t st)
+{
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_alpha2, dim3(1), dim3(256), 0, st, alpha, n, a2, stats);
+    const int rounds = 14;   // 17^14 > 2^57
+    hipLaunchKernelGGL(k_bisect, dim3(cdiv(count, 256 / BIS_NS)), dim3(256), 0, st, (const double *)a2, n, first,
+                       count, (const double *)stats, rounds, w);
+}
+
+void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
+                            double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
+                            double *Q, int ldq, hipStream_t st)
+{
+    if (nev <= 0) return;
+    hipLaunchKernelGGL(k_invit, dim3(cdiv(nev, 256)), dim3(256), 0, st, alpha, n, nev, w, stats, 3, U0, U1, U2,
+                       Lm, Sw, Y);
+    if (n & 1) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, alpha, n, nev, Y);
+    hipLaunchKernelGGL(k_transpose, dim3(cdiv(nev, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Y, n,
+                       nev, Q, ldq);
+}
+
+void launch_chol_inv(const double *Gp, int nparts, int NB, double *Rinv, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, st, Gp, nparts, NB, Rinv);
+}
+
+}  // namespace skew

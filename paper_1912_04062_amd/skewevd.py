@@ -1,0 +1,269 @@
+"""Python binding of the skew-symmetric eigensolver library (libskewevd.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C-ABI of include/skew_evd.h.  PyTorch supplies device
+memory and the current stream.  The library must have been built (see
+paper_1912_04062_amd/build.py); importing this module without it raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libskewevd.so")
+
+OK = 0
+ERR_NONFINITE = 1
+ERR_NOCONV = 2
+WARN_REFINE = 3
+ERR_NOMEM = 4
+ERR_HIP = 5
+ERR_NODEVICE = 6
+
+PREC_FP64 = 0
+PREC_FP32_REFINE = 1
+_PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32_REFINE, "fp32_refine": PREC_FP32_REFINE}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("band", ctypes.c_int),
+                ("max_refine_sweeps", ctypes.c_int), ("refine_tol", ctypes.c_double),
+                ("workspace_limit", ctypes.c_size_t), ("reserved", ctypes.c_int * 8)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("ms_stage", ctypes.c_double * 8),
+                ("band", ctypes.c_int), ("refine_sweeps", ctypes.c_int),
+                ("refine_residual", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t)]
+
+    STAGES = ("ingest", "full_to_band", "bulge_chase", "tridiag_solve", "bt2", "bt1",
+              "refine", "copy_out")
+
+    def as_dict(self):
+        d = {"ms_total": self.ms_total, "band": self.band, "refine_sweeps": self.refine_sweeps,
+             "refine_residual": self.refine_residual, "workspace_bytes": int(self.workspace_bytes)}
+        d["ms_stage"] = {k: self.ms_stage[i] for i, k in enumerate(self.STAGES)}
+        return d
+
+
+class SkewEvdError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: status {status}: {status_string(status)}")
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1912_04062_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.skew_evd_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.skew_evd_default_opts.restype = None
+    lib.skew_evd_create.argtypes = [ctypes.POINTER(vp), vp]
+    lib.skew_evd_create.restype = ip
+    lib.skew_evd_destroy.argtypes = [vp]
+    lib.skew_evd_destroy.restype = ip
+    lib.skew_evd_ex.argtypes = [vp, ip, vp, ip, ip, vp, vp, ip, vp, ip, ctypes.POINTER(Opts),
+                                ctypes.POINTER(Info)]
+    lib.skew_evd_ex.restype = ip
+    lib.skew_evd.argtypes = [ip, vp, ip, ip, vp, vp, vp]
+    lib.skew_evd.restype = ip
+    lib.skew_evd_batched.argtypes = [vp, ip, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts),
+                                     ctypes.POINTER(Info), vp]
+    lib.skew_evd_batched.restype = ip
+    lib.skew_evd_band_reduce.argtypes = [vp, ip, vp, ip, ip, vp, ip]
+    lib.skew_evd_band_reduce.restype = ip
+    lib.skew_evd_tridiagonalize.argtypes = [vp, ip, vp, ip, ip, vp]
+    lib.skew_evd_tridiagonalize.restype = ip
+    lib.skew_evd_tridiag_eig.argtypes = [vp, ip, vp, ip, vp, vp, ip]
+    lib.skew_evd_tridiag_eig.restype = ip
+    lib.skew_evd_status_string.argtypes = [ip]
+    lib.skew_evd_status_string.restype = ctypes.c_char_p
+    lib.skew_evd_version.argtypes = []
+    lib.skew_evd_version.restype = ip
+    _lib = lib
+    return lib
+
+
+def lib():
+    return _load()
+
+
+def status_string(status):
+    return _load().skew_evd_status_string(int(status)).decode()
+
+
+def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=None,
+                 workspace_limit=0):
+    o = Opts()
+    _load().skew_evd_default_opts(ctypes.byref(o))
+    o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    o.band = int(band)
+    if max_refine_sweeps is not None:
+        o.max_refine_sweeps = int(max_refine_sweeps)
+    if refine_tol is not None:
+        o.refine_tol = float(refine_tol)
+    o.workspace_limit = int(workspace_limit)
+    return o
+
+
+def colmajor(A):
+    """(tensor, ld) whose memory holds A column-major (a copy unless it already does)."""
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    n, m = A.shape
+    if A.stride(0) == 1 and A.stride(1) >= max(1, n):
+        return A, A.stride(1)
+    t = A.t().contiguous().t()
+    return t, max(1, n)
+
+
+def empty_colmajor(n, k, device, dtype=torch.float64):
+    return torch.empty((k, n), dtype=dtype, device=device).t()
+
+
+class Handle:
+    """A solver handle bound to the current device and a torch stream."""
+
+    def __init__(self, stream=None):
+        self._lib = _load()
+        stream = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self._lib.skew_evd_create(ctypes.byref(h), ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise SkewEvdError(st, "skew_evd_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.skew_evd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- solver --------------------------------------------------------------
+    def solve(self, A, nev=None, precision="fp64", band=0, opts=None, info=None, out=None,
+              check=True):
+        """Eigenpairs of the skew-symmetric A (torch float64 CUDA tensor, n x n).
+
+        Returns (lam, Zre, Zim): lam (nev,), Zre/Zim (n, nev) column-major
+        views.  Only the strict lower triangle of A is read.
+        """
+        n = A.shape[0]
+        half = (n + 1) // 2
+        nev = half if nev is None else int(nev)
+        Ac, lda = colmajor(A)
+        dev = A.device
+        if out is None:
+            lam = torch.empty(max(nev, 1), dtype=torch.float64, device=dev)
+            zr = empty_colmajor(max(n, 1), max(nev, 1), dev)
+            zi = empty_colmajor(max(n, 1), max(nev, 1), dev)
+        else:
+            lam, zr, zi = out
+        o = opts if opts is not None else default_opts(precision, band)
+        inf = info if info is not None else Info()
+        st = self._lib.skew_evd_ex(self._h, n, ctypes.c_void_p(Ac.data_ptr()), lda, nev,
+                                   ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(zr.data_ptr()),
+                                   zr.stride(1), ctypes.c_void_p(zi.data_ptr()), zi.stride(1),
+                                   ctypes.byref(o), ctypes.byref(inf))
+        if check and st not in (OK, WARN_REFINE):
+            raise SkewEvdError(st, "skew_evd_ex")
+        self.last_status = st
+        self.last_info = inf
+        return lam[:nev], zr[:n, :nev], zi[:n, :nev]
+
+    def solve_batched(self, mats, precision="fp64", band=0):
+        """Solve a list of skew matrices (each n_i x n_i float64 CUDA); returns
+        a list of (lam, Zre, Zim) and the per-problem status list."""
+        count = len(mats)
+        cols = [colmajor(A) for A in mats]
+        ns = [int(A.shape[0]) for A in mats]
+        nevs = [(x + 1) // 2 for x in ns]
+        dev = mats[0].device if mats else torch.device("cuda")
+        outs = [(torch.empty(max(v, 1), dtype=torch.float64, device=dev),
+                 empty_colmajor(max(x, 1), max(v, 1), dev),
+                 empty_colmajor(max(x, 1), max(v, 1), dev)) for x, v in zip(ns, nevs)]
+        IntA = ctypes.c_int * max(count, 1)
+        PtrA = ctypes.c_void_p * max(count, 1)
+        n_a = IntA(*ns)
+        lda_a = IntA(*[ld for _, ld in cols])
+        nev_a = IntA(*nevs)
+        A_a = PtrA(*[c.data_ptr() for c, _ in cols])
+        l_a = PtrA(*[o[0].data_ptr() for o in outs])
+        zr_a = PtrA(*[o[1].data_ptr() for o in outs])
+        zi_a = PtrA(*[o[2].data_ptr() for o in outs])
+        status = IntA()
+        o = default_opts(precision, band)
+        inf = Info()
+        st = self._lib.skew_evd_batched(self._h, count, n_a, A_a, lda_a, nev_a, l_a, zr_a, zi_a,
+                                        ctypes.byref(o), ctypes.byref(inf), status)
+        self.last_info = inf
+        res = [(lm[:v], zr[:x, :v], zi[:x, :v]) for (lm, zr, zi), x, v in zip(outs, ns, nevs)]
+        return res, [status[i] for i in range(count)], st
+
+    # -- stage entry points --------------------------------------------------
+    def band_reduce(self, A, b):
+        n = A.shape[0]
+        Ac, lda = colmajor(A)
+        band = empty_colmajor(b + 1, max(n, 1), A.device)
+        st = self._lib.skew_evd_band_reduce(self._h, n, ctypes.c_void_p(Ac.data_ptr()), lda, b,
+                                            ctypes.c_void_p(band.data_ptr()), band.stride(1))
+        if st != OK:
+            raise SkewEvdError(st, "skew_evd_band_reduce")
+        return band[:, :n]
+
+    def tridiagonalize(self, A, b=0):
+        n = A.shape[0]
+        Ac, lda = colmajor(A)
+        alpha = torch.empty(max(n - 1, 1), dtype=torch.float64, device=A.device)
+        st = self._lib.skew_evd_tridiagonalize(self._h, n, ctypes.c_void_p(Ac.data_ptr()), lda, b,
+                                               ctypes.c_void_p(alpha.data_ptr()))
+        if st != OK:
+            raise SkewEvdError(st, "skew_evd_tridiagonalize")
+        return alpha[:max(n - 1, 0)]
+
+    def tridiag_eig(self, alpha, nev=None):
+        n = alpha.numel() + 1
+        nev = (n + 1) // 2 if nev is None else int(nev)
+        a = alpha.contiguous() if alpha.numel() else torch.zeros(1, dtype=torch.float64,
+                                                                  device=alpha.device)
+        lam = torch.empty(max(nev, 1), dtype=torch.float64, device=alpha.device)
+        Q = empty_colmajor(n, max(nev, 1), alpha.device)
+        st = self._lib.skew_evd_tridiag_eig(self._h, n, ctypes.c_void_p(a.data_ptr()), nev,
+                                            ctypes.c_void_p(lam.data_ptr()),
+                                            ctypes.c_void_p(Q.data_ptr()), Q.stride(1))
+        if st != OK:
+            raise SkewEvdError(st, "skew_evd_tridiag_eig")
+        return lam[:nev], Q[:, :nev]
+
+
+_handles = {}
+
+
+def handle():
+    """Per-device default handle on the current stream."""
+    dev = torch.cuda.current_device()
+    s = torch.cuda.current_stream()
+    key = (dev, s.cuda_stream)
+    if key not in _handles:
+        _handles[key] = Handle(s)
+    return _handles[key]
+
+
+def skew_evd(A, nev=None, precision="fp64", band=0):
+    """Convenience: (lam, Z) with Z = Zre + i Zim as a complex128 tensor."""
+    lam, zr, zi = handle().solve(A, nev=nev, precision=precision, band=band)
+    return lam, torch.complex(zr.contiguous(), zi.contiguous())

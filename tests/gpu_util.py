@@ -1,0 +1,57 @@
+"""Helpers for the GPU tests: device inputs, tolerance metrics (FP64, CPU)."""
+import numpy as np
+import torch
+
+# Tolerances of the parity contract (FP64): eigenvalue error <= 1e-12 ||A||,
+# residual ||A Z - Z diag(i lam)||_F / (n ||A||) <= 1e-13,
+# orthogonality ||Z^H Z - I||_F / n <= 1e-13.
+TOL_EIG = 1e-12
+TOL_RES = 1e-13
+TOL_ORTH = 1e-13
+
+
+def to_dev(A):
+    """numpy (column-major) -> CUDA float64 tensor holding A column-major."""
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(A, dtype=np.float64).T)).cuda()
+    return t.t()          # (n, n) view with strides (1, n)
+
+
+def metrics(A, lam, Z, norm=None):
+    """(residual, orthogonality, ||A||) in FP64 on the CPU."""
+    n = A.shape[0]
+    if norm is None:
+        norm = float(np.max(lam)) if lam.size else 0.0
+    norm = max(norm, 1e-300)
+    R = A @ Z - Z * (1j * lam)[None, :]
+    res = np.linalg.norm(R) / (n * norm)
+    orth = np.linalg.norm(Z.conj().T @ Z - np.eye(Z.shape[1])) / n
+    return res, orth, norm
+
+
+def solve_np(h, A, nev=None, **kw):
+    lam, zr, zi = h.solve(to_dev(A), nev=nev, **kw)
+    torch.cuda.synchronize()
+    return lam.cpu().numpy(), zr.cpu().numpy() + 1j * zi.cpu().numpy()
+
+
+def band_to_dense(band, n, b):
+    B = np.zeros((n, n))
+    for j in range(n):
+        for d in range(1, b + 1):
+            if j + d < n:
+                B[j + d, j] = band[d, j]
+                B[j, j + d] = -band[d, j]
+    return B
+
+
+def phase_match(Z, Zref, lam, gap_tol, tol):
+    """For eigenvalues separated by more than gap_tol from their neighbours,
+    |<z_ref, z>| >= 1 - tol (eigenvectors agree up to a unit phase)."""
+    worst = 0.0
+    for k in range(len(lam)):
+        lo = lam[k - 1] if k > 0 else -np.inf
+        hi = lam[k + 1] if k + 1 < len(lam) else np.inf
+        gap = min(lam[k] - lo, hi - lam[k], 2 * lam[k] if lam[k] > 0 else np.inf)
+        if gap > gap_tol:
+            worst = max(worst, 1.0 - abs(np.vdot(Zref[:, k], Z[:, k])))
+    return worst <= tol, worst

@@ -1,0 +1,73 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every function the
+header declares, and validates arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "skew_evd.h")
+LIB = os.path.join(ROOT, "paper_1912_04062_amd", "libskewevd.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(?:int|void|const char \*)\s*\*?\s*(skew_evd\w*)\s*\(", txt)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1912_04062_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ["skew_evd", "skew_evd_ex", "skew_evd_batched", "skew_evd_create",
+                 "skew_evd_destroy", "skew_evd_status_string", "skew_evd_band_reduce",
+                 "skew_evd_tridiagonalize", "skew_evd_tridiag_eig", "skew_evd_default_opts",
+                 "skew_evd_version"]:
+        assert must in names
+
+
+def test_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_argument_validation_without_device(lib):
+    vp = ctypes.c_void_p
+    lib.skew_evd.argtypes = [ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    assert lib.skew_evd(-1, None, 1, 0, None, None, None) == -1
+    assert lib.skew_evd(4, None, 4, 1, None, None, None) == -2
+    assert lib.skew_evd(4, vp(8), 3, 1, None, None, None) == -3
+    assert lib.skew_evd(4, vp(8), 4, 3, None, None, None) == -4
+    assert lib.skew_evd(4, vp(8), 4, 2, None, None, None) == -5
+    assert lib.skew_evd(4, vp(8), 4, 2, vp(8), None, None) == -6
+    assert lib.skew_evd(4, vp(8), 4, 2, vp(8), vp(8), None) == -7
+    assert lib.skew_evd(0, None, 1, 0, None, None, None) == 0
+    lib.skew_evd_ex.restype = ctypes.c_int
+    assert lib.skew_evd_ex(None, 4, vp(8), 4, 1, vp(8), vp(8), 4, vp(8), 4, None, None) == -1
+
+
+def test_status_strings(lib):
+    lib.skew_evd_status_string.restype = ctypes.c_char_p
+    lib.skew_evd_status_string.argtypes = [ctypes.c_int]
+    for code in range(0, 7):
+        assert lib.skew_evd_status_string(code)
+    assert b"invalid" in lib.skew_evd_status_string(-3)
+    assert lib.skew_evd_version() >= 100
+
+
+def test_oracle_shares_nothing_with_the_library():
+    """The oracle is plain C with no include of the library's sources."""
+    src = open(os.path.join(ROOT, "oracle", "skew_oracle.c")).read()
+    assert "skew_evd.h" not in src and "csrc" not in src
+    for f in os.listdir(os.path.join(ROOT, "paper_1912_04062_amd", "csrc")):
+        txt = open(os.path.join(ROOT, "paper_1912_04062_amd", "csrc", f)).read()
+        assert "oracle" not in txt.lower()
