@@ -1,0 +1,126 @@
+"""Benchmark: skew-symmetric eigensolver time-to-solution on one MI355X.
+
+One step = one complete solve (every stage: full-to-band, bulge chase,
+tridiagonal solve, D scaling, both back-transformations, and for the precision
+form the refinement) of a dense random skew-symmetric A of order n = 16384
+(A = (B - B^T)/2, B iid N(0, 1), seed 4) with n/2 eigenpairs, inputs resident
+in HBM.  value = useful FLOP rate F / time, F = (4/3) n^3 + 8 n^2 nev (the
+tridiagonalization plus two back-transformations of 2*nev real columns).
+
+Prints ONE JSON line (rank 0).  The roofline object describes the kernel that
+takes the largest share of the step, timed with HIP events on the library's
+stream; cpu_baseline is the FP64 oracle timed on a bounded sample on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3}          # TFLOP/s, dense MFMA/vector
+HBM_PEAK = 8000.0                           # GB/s
+
+
+def useful_flops(n, nev):
+    return 4.0 / 3.0 * n ** 3 + 8.0 * n * n * nev
+
+
+def cpu_baseline(sample_n=3072):
+    import oracle
+    from paper_1912_04062_amd import workloads
+    A = workloads.random_skew(sample_n, 4)
+    t0 = time.perf_counter()
+    oracle.skew_evd(A)
+    dt = time.perf_counter() - t0
+    f = useful_flops(sample_n, (sample_n + 1) // 2)
+    return {"value": f / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one full oracle solve of a random skew matrix n={sample_n} "
+                      f"(nev={(sample_n + 1) // 2}), {dt:.1f} s; TFLOP/s with the same useful-flop "
+                      f"count F(n) as the GPU line"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=3072)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1912_04062_amd import skewevd, workloads
+
+    n = args.n
+    nev = (n + 1) // 2
+    A = workloads.random_skew(n, 4)
+    Ad = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+    del A
+    h = skewevd.Handle()
+    out = (torch.empty(nev, dtype=torch.float64, device="cuda"),
+           skewevd.empty_colmajor(n, nev, "cuda"), skewevd.empty_colmajor(n, nev, "cuda"))
+    for _ in range(args.warmup):
+        h.solve(Ad, precision=args.precision, out=out)
+    torch.cuda.synchronize()
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.solve(Ad, precision=args.precision, out=out, profile=1)
+        infos.append(h.last_info.as_dict())
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    ms = wall * 1e3
+    F = useful_flops(n, nev)
+    value = F / wall / 1e12
+
+    # dominant kernel: the stage with the largest average device time
+    stage_avg = {k: float(np.mean([i["ms_stage"][k] for i in infos])) for k in infos[0]["ms_stage"]}
+    kern = {k: float(np.mean([i["kernels"][k]["ms"] for i in infos])) for k in infos[0]["kernels"]}
+    dom = max(kern, key=kern.get)
+    kinfo = infos[0]["kernels"][dom]
+    dtype = "f64" if args.precision == "fp64" else "f32"
+    if kinfo["bound"] == "hbm":
+        achieved = kinfo["bytes"] / (kern[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s"}
+    else:
+        achieved = kinfo["flops"] / (kern[dom] * 1e-3) / 1e12
+        roof = {"bound": kinfo["bound"], "achieved": achieved,
+                "peak": PEAK[kinfo.get("dtype", dtype)], "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["launches_per_step"] = kinfo["launches"]
+    roof["ms_per_step"] = kern[dom]
+
+    line = {
+        "metric": "skew-EVD time-to-solution n=16384, n/2 eigvecs: FP32+refine vs FP64, TFLOP/s",
+        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"dense random skew-symmetric A=(B-B^T)/2, B iid N(0,1), seed 4, "
+                               f"n={n}, nev={nev}, {args.precision} form",
+                   "n": n, "nev": nev, "precision": args.precision, "band": infos[0]["band"],
+                   "useful_flops": F},
+        "stages_ms": stage_avg,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -59,8 +59,32 @@ typedef struct skew_evd_opts {
     double refine_tol;      /* precision form: stop when the normalised
                                residual estimate is below this (default 1e-14) */
     size_t workspace_limit; /* bytes; 0 = unlimited.  Exceeding it returns NOMEM */
-    int reserved[8];
+    int profile;            /* 1: time the main kernels with HIP events (info->kern) */
+    int reserved[7];
 } skew_evd_opts;
+
+/* Main kernels, for the per-kernel statistics of skew_evd_info. */
+#define SKEW_EVD_K_PANEL 0   /* panel Householder QR (full-to-band) */
+#define SKEW_EVD_K_SYMM 1    /* Y = A V T and W = Y - V X / 2 (full-to-band) */
+#define SKEW_EVD_K_SYR2K 2   /* A += V W^T - W V^T (full-to-band) */
+#define SKEW_EVD_K_CHASE 3   /* bulge chasing */
+#define SKEW_EVD_K_TRIDIAG 4 /* bisection, inverse iteration, Gram-Schmidt */
+#define SKEW_EVD_K_BT2 5     /* stage-2 back-transformation (incl. D and T factors) */
+#define SKEW_EVD_K_BT1 6     /* stage-1 back-transformation */
+#define SKEW_EVD_K_REFINE 7  /* refinement (precision form) */
+#define SKEW_EVD_NKERN 8
+
+#define SKEW_EVD_BOUND_MFMA 0
+#define SKEW_EVD_BOUND_HBM 1
+#define SKEW_EVD_BOUND_ALU 2
+
+typedef struct skew_evd_kstat {
+    double ms;              /* summed device time of the kernel's launches */
+    double flops;           /* algorithmic flop count of those launches */
+    double bytes;           /* algorithmic HBM bytes of those launches */
+    int launches;           /* number of launches timed */
+    int bound;              /* SKEW_EVD_BOUND_* : the roofline that bounds it */
+} skew_evd_kstat;
 
 typedef struct skew_evd_info {
     double ms_total;        /* device time of the whole call (HIP events) */
@@ -71,6 +95,7 @@ typedef struct skew_evd_info {
     int refine_sweeps;      /* sweeps performed (precision form) */
     double refine_residual; /* last normalised residual estimate (precision form) */
     size_t workspace_bytes; /* device workspace held by the handle */
+    skew_evd_kstat kern[SKEW_EVD_NKERN]; /* filled when opts.profile = 1 */
 } skew_evd_info;
 
 typedef struct skew_evd_handle_s *skew_evd_handle;

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 #include <algorithm>
+#include <thread>
 #include <vector>
 
 #include "../../include/skew_evd.h"
@@ -47,6 +48,19 @@ struct skew_evd_handle_s {
     size_t ws_bytes = 0;
     hipEvent_t ev[NSTAGE_EV] = {};
     unsigned *ctl_host = nullptr;   // pinned copy of the control words
+    // per-kernel timing (opts.profile)
+    bool prof = false;
+    std::vector<hipEvent_t> kev;
+    size_t kev_used = 0;
+    struct KRec { int kid; size_t e0, e1; };
+    std::vector<KRec> krec;
+    size_t kopen[SKEW_EVD_NKERN] = {};
+    int refine_passes = 0;
+    int *goff_host = nullptr;       // pinned group offsets of the bulge-chase reflectors
+    size_t goff_cap = 0;
+    // batched form: sub-handles, each with its own stream and workspace
+    std::vector<skew_evd_handle> sub;
+    std::vector<hipStream_t> sub_streams;
 };
 
 namespace {
@@ -55,7 +69,8 @@ namespace {
 // Workspace layout.  Offsets are 256-byte aligned.
 struct Layout {
     size_t W, Vall, Tall, tauall, Ypart, Y0, Wd, Gp, Tx, part, ab, goff, V2, tau2, T2, V2t, alpha, a2, stats,
-        lam, U0, U1, U2, Lm, Sw, Yiv, Qd, Z, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, total;
+        lam, U0, U1, U2, Lm, Sw, Yiv, Qd, Z, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
+        rstat, total;
     std::vector<size_t> Voff;
 };
 
@@ -119,6 +134,20 @@ Layout plan_layout(const Plan &p)
     L.Rinv = take(sizeof(double) * ORTH_NB * ORTH_NB);
     L.Tmp = take(sizeof(double) * n * ORTH_NB);
     L.ctl = take(sizeof(unsigned) * (64 + n));
+    if (p.prec) {
+        const size_t ncx = n;   // 2 nev columns (2 nev - 1 for odd n); nev = ceil(n/2) for the full half
+        const size_t nc = std::max((size_t)2 * nev, ncx);
+        L.rX = take(sizeof(double) * n * nc);
+        L.rXn = take(sizeof(double) * n * nc);
+        L.rP = take(sizeof(double) * n * nc);
+        L.rS = take(sizeof(double) * nc * nc);
+        L.rG = take(sizeof(double) * nc * nc);
+        L.rE = take(sizeof(float) * nc * nc);
+        L.rlam = take(sizeof(double) * (nev + 1));
+        L.rstat = take(sizeof(double) * 8);
+    } else {
+        L.rX = L.rXn = L.rP = L.rS = L.rG = L.rE = L.rlam = L.rstat = 0;
+    }
     L.total = off;
     return L;
 }
@@ -175,6 +204,86 @@ int ensure_ws(skew_evd_handle h, size_t bytes, size_t limit)
 
 template <typename T> T *ptr(skew_evd_handle h, size_t off) { return (T *)(h->ws + off); }
 
+// Kernel timers: an event before and after the launches of a main kernel.
+hipError_t kt_event(skew_evd_handle h, size_t *idx)
+{
+    if (h->kev_used == h->kev.size()) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        h->kev.push_back(e);
+    }
+    *idx = h->kev_used++;
+    return hipEventRecord(h->kev[*idx], h->stream);
+}
+hipError_t kt_begin(skew_evd_handle h, int kid)
+{
+    if (!h->prof) return hipSuccess;
+    return kt_event(h, &h->kopen[kid]);
+}
+hipError_t kt_end(skew_evd_handle h, int kid)
+{
+    if (!h->prof) return hipSuccess;
+    size_t e1;
+    hipError_t r = kt_event(h, &e1);
+    h->krec.push_back({kid, h->kopen[kid], e1});
+    return r;
+}
+void kt_reset(skew_evd_handle h, bool on)
+{
+    h->prof = on;
+    h->kev_used = 0;
+    h->krec.clear();
+}
+// after synchronisation
+void kt_collect(skew_evd_handle h, skew_evd_info *info)
+{
+    if (!info || !h->prof) return;
+    for (const auto &r : h->krec) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->kev[r.e0], h->kev[r.e1]) == hipSuccess) {
+            info->kern[r.kid].ms += ms;
+            info->kern[r.kid].launches += 1;
+        }
+    }
+}
+
+// Algorithmic flop and byte counts of the main kernels for a plan.
+void kt_counts(const struct Plan &p, skew_evd_info *info)
+{
+    if (!info) return;
+    const double n = p.n, nev = p.nev, b = p.b, es = p.prec ? 4.0 : 8.0;
+    double sm = 0.0, sm2 = 0.0;
+    for (int j = 0; j < p.npanels; ++j) {
+        double m = n - (double)(j + 1) * b;
+        sm += m;
+        sm2 += m * m;
+    }
+    skew_evd_kstat *k = info->kern;
+    k[SKEW_EVD_K_PANEL].flops = 2.0 * sm * b * b;
+    k[SKEW_EVD_K_PANEL].bytes = 2.0 * es * sm * b;
+    k[SKEW_EVD_K_PANEL].bound = SKEW_EVD_BOUND_ALU;
+    k[SKEW_EVD_K_SYMM].flops = 2.0 * sm2 * b + 6.0 * sm * b * b;
+    k[SKEW_EVD_K_SYMM].bytes = es * sm2 / 2.0;
+    k[SKEW_EVD_K_SYMM].bound = SKEW_EVD_BOUND_MFMA;
+    k[SKEW_EVD_K_SYR2K].flops = 2.0 * sm2 * b;
+    k[SKEW_EVD_K_SYR2K].bytes = es * sm2;
+    k[SKEW_EVD_K_SYR2K].bound = SKEW_EVD_BOUND_MFMA;
+    k[SKEW_EVD_K_CHASE].flops = 6.0 * n * n * b;
+    k[SKEW_EVD_K_CHASE].bytes = 8.0 * (2.0 * b + 1.0) * n * 2.0 + 8.0 * n * n / 2.0;
+    k[SKEW_EVD_K_CHASE].bound = SKEW_EVD_BOUND_ALU;
+    k[SKEW_EVD_K_TRIDIAG].flops = 3.0 * 14.0 * 16.0 * n * nev + 4.0 * n * nev * p.orth_window;
+    k[SKEW_EVD_K_TRIDIAG].bytes = 8.0 * n * nev * 8.0;
+    k[SKEW_EVD_K_TRIDIAG].bound = SKEW_EVD_BOUND_ALU;
+    k[SKEW_EVD_K_BT2].flops = 4.0 * n * n * nev;
+    k[SKEW_EVD_K_BT2].bytes = es * (2.0 * 2.0 * n * nev + n * n / 2.0);
+    k[SKEW_EVD_K_BT2].bound = SKEW_EVD_BOUND_MFMA;
+    k[SKEW_EVD_K_BT1].flops = 8.0 * b * nev * sm;
+    k[SKEW_EVD_K_BT1].bytes = es * 3.0 * sm * 2.0 * nev;
+    k[SKEW_EVD_K_BT1].bound = SKEW_EVD_BOUND_MFMA;
+    k[SKEW_EVD_K_REFINE].bound = SKEW_EVD_BOUND_MFMA;
+}
+
 // ---------------------------------------------------------------------------
 // Stage drivers.  All enqueue on h->stream.
 
@@ -187,23 +296,27 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
     unsigned *ctl = ptr<unsigned>(h, L.ctl);
     skew::launch_ingest<T>(A, lda, n, W, n, ctl + CTL_FLAGS, st);
     HCHK(hipGetLastError());
-    if (check_finite) {
-        HCHK(hipMemcpyAsync(h->ctl_host, ctl, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, st));
-        HCHK(hipStreamSynchronize(st));
-        if (h->ctl_host[CTL_FLAGS] & 1u) return SKEW_EVD_ERR_NONFINITE;
-    }
+    (void)check_finite;   // the non-finite flag is read when the call completes
     HCHK(hipEventRecord(h->ev[1], st));
     unsigned bar_base = 0;
     for (int j = 0; j < p.npanels; ++j) {
         const int c0 = j * b, r0 = c0 + b, m = n - r0;
         T *Vd = ptr<T>(h, L.Vall) + L.Voff[j];
         double *Tf = ptr<double>(h, L.Tall) + (size_t)j * b * b;
+        HCHK(kt_begin(h, SKEW_EVD_K_PANEL));
         HCHK(skew::launch_panel_qr<T>(W, n, c0, r0, m, b, Vd, ptr<double>(h, L.tauall) + (size_t)j * b, Tf,
                                       ptr<double>(h, L.part), ctl + CTL_BAR, bar_base, ctl + CTL_ERR, st));
+        HCHK(kt_end(h, SKEW_EVD_K_PANEL));
         bar_base += (unsigned)((std::min(m, b) + 1) * skew::panel_qr_groups(m));
-        if (m > 1)
-            skew::launch_stage1_update<T>(W, n, r0, m, b, Vd, Tf, ptr<T>(h, L.Ypart), ptr<T>(h, L.Y0),
-                                          ptr<T>(h, L.Wd), ptr<double>(h, L.Gp), ptr<T>(h, L.Tx), st);
+        if (m > 1) {
+            HCHK(kt_begin(h, SKEW_EVD_K_SYMM));
+            skew::launch_stage1_w<T>(W, n, r0, m, b, Vd, Tf, ptr<T>(h, L.Ypart), ptr<T>(h, L.Y0), ptr<T>(h, L.Wd),
+                                     ptr<double>(h, L.Gp), ptr<T>(h, L.Tx), st);
+            HCHK(kt_end(h, SKEW_EVD_K_SYMM));
+            HCHK(kt_begin(h, SKEW_EVD_K_SYR2K));
+            skew::launch_stage1_syr2k<T>(W, n, r0, m, b, Vd, ptr<T>(h, L.Wd), st);
+            HCHK(kt_end(h, SKEW_EVD_K_SYR2K));
+        }
         HCHK(hipGetLastError());
     }
     skew::launch_band_extract<T>(W, n, n, b, ptr<double>(h, L.ab), 2 * b + 1, st);
@@ -216,20 +329,27 @@ int stage_chase(skew_evd_handle h, const Plan &p, const Layout &L)
 {
     hipStream_t st = h->stream;
     const int n = p.n, b = p.b;
-    std::vector<int> goff(p.nsig + 2, 0);
-    skew::chase_ngroups(n, b, p.nb2, goff.data());
-    HCHK(hipMemcpyAsync(ptr<int>(h, L.goff), goff.data(), sizeof(int) * (p.nsig + 1), hipMemcpyHostToDevice, st));
+    if ((size_t)(p.nsig + 2) > h->goff_cap) {
+        if (h->goff_host) HCHK(hipHostFree(h->goff_host));
+        h->goff_host = nullptr;
+        h->goff_cap = 0;
+        HCHK(hipHostMalloc((void **)&h->goff_host, sizeof(int) * (p.nsig + 2), hipHostMallocDefault));
+        h->goff_cap = p.nsig + 2;
+    }
+    int *goff = h->goff_host;
+    skew::chase_ngroups(n, b, p.nb2, goff);
+    HCHK(hipMemcpyAsync(ptr<int>(h, L.goff), goff, sizeof(int) * (p.nsig + 1), hipMemcpyHostToDevice, st));
     if (p.ngroups > 0) {
         HCHK(hipMemsetAsync(ptr<double>(h, L.V2), 0, sizeof(double) * (size_t)p.ngroups * b * p.nb2, st));
         HCHK(hipMemsetAsync(ptr<double>(h, L.tau2), 0, sizeof(double) * (size_t)p.ngroups * p.nb2, st));
     }
     unsigned *ctl = ptr<unsigned>(h, L.ctl);
     HCHK(hipMemsetAsync(ctl + CTL_PROGRESS, 0, sizeof(unsigned) * n, st));
+    HCHK(kt_begin(h, SKEW_EVD_K_CHASE));
     HCHK(skew::launch_chase(ptr<double>(h, L.ab), 2 * b + 1, n, b, p.nb2, ptr<double>(h, L.V2),
                             ptr<double>(h, L.tau2), ptr<int>(h, L.goff), ctl + CTL_PROGRESS, ctl + CTL_ERR,
                             ptr<double>(h, L.alpha), st));
-    // the goff host vector must outlive the async copy
-    HCHK(hipStreamSynchronize(st));
+    HCHK(kt_end(h, SKEW_EVD_K_CHASE));
     HCHK(hipEventRecord(h->ev[3], st));
     return SKEW_EVD_OK;
 }
@@ -265,6 +385,7 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
 {
     hipStream_t st = h->stream;
     const int n = p.n;
+    HCHK(kt_begin(h, SKEW_EVD_K_TRIDIAG));
     skew::launch_tridiag_eigvals(alpha, n, n / 2, nev, ptr<double>(h, L.a2), ptr<double>(h, L.stats), lam, st);
     skew::launch_tridiag_eigvecs(alpha, n, nev, lam, ptr<double>(h, L.stats), ptr<double>(h, L.U0),
                                  ptr<double>(h, L.U1), ptr<double>(h, L.U2), ptr<double>(h, L.Lm),
@@ -272,6 +393,7 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
     HCHK(hipGetLastError());
     int rc = orthogonalize(h, p, L, Q, ldq, n, nev);
     if (rc) return rc;
+    HCHK(kt_end(h, SKEW_EVD_K_TRIDIAG));
     HCHK(hipEventRecord(h->ev[4], st));
     return SKEW_EVD_OK;
 }
@@ -282,18 +404,22 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L)
     hipStream_t st = h->stream;
     const int n = p.n, nev = p.nev, b = p.b;
     T *Z = ptr<T>(h, L.Z);
+    HCHK(kt_begin(h, SKEW_EVD_K_BT2));
     skew::launch_dscale<T>(ptr<double>(h, L.Qd), n, n, nev, Z, n, st);
     skew::launch_bt2<T>(Z, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2), ptr<T>(h, L.T2),
                         p.prec ? ptr<T>(h, L.V2t) : nullptr, ptr<int>(h, L.goff), p.nsig, p.ngroups, st);
+    HCHK(kt_end(h, SKEW_EVD_K_BT2));
     HCHK(hipGetLastError());
     HCHK(hipEventRecord(h->ev[5], st));
     for (int j = p.npanels - 1; j >= 0; --j) {
         const int r0 = (j + 1) * b, m = n - r0;
         const T *Vd = ptr<T>(h, L.Vall) + L.Voff[j];
         const double *Tf = ptr<double>(h, L.Tall) + (size_t)j * b * b;
+        HCHK(kt_begin(h, SKEW_EVD_K_BT1));
         int S = skew::launch_gemm_tn_part<T>(Vd, m, Z + r0, n, b, 2 * nev, m, ptr<double>(h, L.Wp), st);
         skew::launch_reduce_left(Tf, ptr<double>(h, L.Wp), S, b, 2 * nev, ptr<double>(h, L.Wt2), st);
         skew::launch_gemm_nn<T>(Vd, m, ptr<double>(h, L.Wt2), 1, m, 2 * nev, b, Z + r0, n, -1.0, 1, st);
+        HCHK(kt_end(h, SKEW_EVD_K_BT1));
         HCHK(hipGetLastError());
     }
     HCHK(hipEventRecord(h->ev[6], st));
@@ -305,6 +431,7 @@ int finish_status(skew_evd_handle h, const Layout &L)
     unsigned *ctl = ptr<unsigned>(h, L.ctl);
     HCHK(hipMemcpyAsync(h->ctl_host, ctl, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, h->stream));
     HCHK(hipStreamSynchronize(h->stream));
+    if (h->ctl_host[CTL_FLAGS] & 1u) return SKEW_EVD_ERR_NONFINITE;
     if (h->ctl_host[CTL_ERR]) {
         snprintf(g_errtext, sizeof(g_errtext), "a device-side wait gave up (code %u)", h->ctl_host[CTL_ERR]);
         return SKEW_EVD_ERR_NOCONV;
@@ -332,6 +459,63 @@ int validate_opts(const skew_evd_opts *o)
     return 0;
 }
 
+// Precision form: refine the FP32 pipeline's eigenpairs against the FP64 A.
+// Returns OK or WARN_REFINE; results are written to lambda / Z_re / Z_im.
+int refine(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, int lda, const skew_evd_opts &o,
+           int nev_out, double *lambda, double *Z_re, int ldzr, double *Z_im, int ldzi, int *sweeps_out,
+           double *res_out)
+{
+    hipStream_t st = h->stream;
+    const int n = p.n, nev = p.nev;          // the full half: nev = ceil(n/2)
+    const int odd = n & 1;
+    const int ncx = odd ? 2 * nev - 1 : 2 * nev;
+    const int nblk = nev;
+    double *X = ptr<double>(h, L.rX), *Xn = ptr<double>(h, L.rXn);
+    double *stat = ptr<double>(h, L.rstat);
+    skew::launch_build_x<float>(ptr<float>(h, L.Z), n, n, nev, odd, X, st);
+    HCHK(hipGetLastError());
+    int sweeps = 0;
+    double last = 1.0;
+    bool converged = false;
+    h->refine_passes = 0;
+    for (int sw = 0; sw < std::max(1, o.max_refine_sweeps); ++sw) {
+        ++h->refine_passes;
+        HCHK(hipMemsetAsync(stat, 0, sizeof(double) * 8, st));
+        skew::launch_refine_products(A, lda, n, X, ncx, ptr<double>(h, L.rP), ptr<double>(h, L.rS),
+                                     ptr<double>(h, L.rG), st);
+        skew::launch_refine_eigs(ptr<double>(h, L.rS), ptr<double>(h, L.rG), ncx, nblk, odd, ptr<double>(h, L.rlam),
+                                 stat, st);
+        HCHK(hipGetLastError());
+        double hs[4] = {0, 0, 0, 0};
+        HCHK(hipMemcpyAsync(hs, stat, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+        const double lmax = hs[2] > 0.0 ? hs[2] : 1.0;
+        last = std::max(hs[0], hs[1] / lmax);
+        if (last <= o.refine_tol) {
+            converged = true;
+            break;
+        }
+        if (o.max_refine_sweeps == 0) break;
+        const double omega = 64.0 * 2.220446049250313e-16 * lmax;
+        skew::launch_refine_update(ptr<double>(h, L.rS), ptr<double>(h, L.rG), n, ncx, nblk, odd,
+                                   ptr<double>(h, L.rlam), omega, ptr<float>(h, L.rE), X, Xn, st);
+        HCHK(hipGetLastError());
+        std::swap(X, Xn);
+        ++sweeps;
+        // a Newton step from a residual r leaves about r^2 (quadratic convergence)
+        if (last * last * 1e2 <= o.refine_tol) {
+            converged = true;
+            break;
+        }
+    }
+    HCHK(hipMemcpyAsync(lambda, ptr<double>(h, L.rlam), sizeof(double) * nev_out, hipMemcpyDeviceToDevice, st));
+    skew::launch_split_x(X, n, nev_out, odd, Z_re, ldzr, Z_im, ldzi, st);
+    HCHK(hipGetLastError());
+    *sweeps_out = sweeps;
+    *res_out = last;
+    return converged ? SKEW_EVD_OK : SKEW_EVD_WARN_REFINE;
+}
+
 int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *lambda, double *Z_re, int ldzr,
           double *Z_im, int ldzi, const skew_evd_opts *opts, skew_evd_info *info)
 {
@@ -339,20 +523,21 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     skew_evd_default_opts(&o);
     if (opts) o = *opts;
     const int prec = o.precision;
-    if (prec != SKEW_EVD_PREC_FP64) {
-        snprintf(g_errtext, sizeof(g_errtext), "precision form not available in this build");
-        return -11;
-    }
+    const int nev_out = nev;
+    // the refinement works on the whole invariant half: the precision form
+    // always computes ceil(n/2) pairs and returns the first nev
+    if (prec) nev = (n + 1) / 2;
     Plan p = make_plan(n, nev, o.band, prec);
     Layout L = plan_layout(p);
     int rc = ensure_ws(h, L.total, o.workspace_limit);
     if (rc) return rc;
     hipStream_t st = h->stream;
+    kt_reset(h, o.profile != 0);
     bool rec[NSTAGE_EV] = {};
     HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, st));
     HCHK(hipEventRecord(h->ev[0], st));
     rec[0] = true;
-    rc = stage_band<double>(h, p, L, A, lda, 1);
+    rc = prec ? stage_band<float>(h, p, L, A, lda, 1) : stage_band<double>(h, p, L, A, lda, 1);
     if (rc) return rc;
     rec[1] = rec[2] = true;
     rc = stage_chase(h, p, L);
@@ -361,20 +546,31 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     rc = stage_tridiag(h, p, L, ptr<double>(h, L.alpha), nev, ptr<double>(h, L.lam), ptr<double>(h, L.Qd), n);
     if (rc) return rc;
     rec[4] = true;
-    rc = stage_backtransform<double>(h, p, L);
+    rc = prec ? stage_backtransform<float>(h, p, L) : stage_backtransform<double>(h, p, L);
     if (rc) return rc;
     rec[5] = rec[6] = true;
+    int rsweeps = 0, refine_rc = SKEW_EVD_OK;
+    double rres = 0.0;
+    if (prec) {
+        HCHK(kt_begin(h, SKEW_EVD_K_REFINE));
+        refine_rc = refine(h, p, L, A, lda, o, nev_out, lambda, Z_re, ldzr, Z_im, ldzi, &rsweeps, &rres);
+        if (refine_rc != SKEW_EVD_OK && refine_rc != SKEW_EVD_WARN_REFINE) return refine_rc;
+        HCHK(kt_end(h, SKEW_EVD_K_REFINE));
+    }
     HCHK(hipEventRecord(h->ev[7], st));
     rec[7] = true;
-    HCHK(hipMemcpyAsync(lambda, ptr<double>(h, L.lam), sizeof(double) * nev, hipMemcpyDeviceToDevice, st));
-    const double *Z = ptr<double>(h, L.Z);
-    HCHK(hipMemcpy2DAsync(Z_re, sizeof(double) * ldzr, Z, sizeof(double) * n, sizeof(double) * n, nev,
-                          hipMemcpyDeviceToDevice, st));
-    HCHK(hipMemcpy2DAsync(Z_im, sizeof(double) * ldzi, Z + (size_t)nev * n, sizeof(double) * n,
-                          sizeof(double) * n, nev, hipMemcpyDeviceToDevice, st));
+    if (!prec) {
+        HCHK(hipMemcpyAsync(lambda, ptr<double>(h, L.lam), sizeof(double) * nev, hipMemcpyDeviceToDevice, st));
+        const double *Z = ptr<double>(h, L.Z);
+        HCHK(hipMemcpy2DAsync(Z_re, sizeof(double) * ldzr, Z, sizeof(double) * n, sizeof(double) * n, nev,
+                              hipMemcpyDeviceToDevice, st));
+        HCHK(hipMemcpy2DAsync(Z_im, sizeof(double) * ldzi, Z + (size_t)nev * n, sizeof(double) * n,
+                              sizeof(double) * n, nev, hipMemcpyDeviceToDevice, st));
+    }
     HCHK(hipEventRecord(h->ev[8], st));
     rec[8] = true;
     rc = finish_status(h, L);
+    if (rc == SKEW_EVD_OK) rc = refine_rc;
     // stage slots: 0 ingest, 1 band, 2 chase, 3 tridiag, 4 BT2(+D), 5 BT1, 6 refine (none), 7 copy-out
     if (info) {
         memset(info, 0, sizeof(*info));
@@ -388,7 +584,20 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
             if (hipEventElapsedTime(&ms, h->ev[a[s] == 7 ? 7 : a[s]], h->ev[bnd[s]]) == hipSuccess)
                 info->ms_stage[s] = ms;
         }
+        info->refine_sweeps = rsweeps;
+        info->refine_residual = rres;
+        if (prec) {
+            // refinement: products (ncx^2 n * 2 + two lower halves) per sweep plus X E
+            // per product pass: P = A X (2 n^2 ncx) and the lower halves of X^T P
+            // and X^T X (2 ncx^2 n); per update: X E (2 n ncx^2)
+            const double nd = n, nc = (n & 1) ? 2.0 * nev - 1.0 : 2.0 * nev;
+            info->kern[SKEW_EVD_K_REFINE].flops =
+                h->refine_passes * (2.0 * nd * nd * nc + 2.0 * nc * nc * nd) + rsweeps * 2.0 * nd * nc * nc;
+        }
+        kt_counts(p, info);
+        kt_collect(h, info);
     }
+    kt_reset(h, false);
     return rc;
 }
 
@@ -431,6 +640,10 @@ int skew_evd_destroy(skew_evd_handle h)
     for (int i = 0; i < NSTAGE_EV; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+    if (h->goff_host) (void)hipHostFree(h->goff_host);
+    for (auto e : h->kev) (void)hipEventDestroy(e);
+    for (auto sh : h->sub) skew_evd_destroy(sh);
+    for (auto s2 : h->sub_streams) (void)hipStreamDestroy(s2);
     delete h;
     return SKEW_EVD_OK;
 }
@@ -504,21 +717,74 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
         return -12;
     }
     if (validate_opts(opts)) return -10;
-    int first = 0;
-    skew_evd_info acc;
-    memset(&acc, 0, sizeof(acc));
-    for (int i = 0; i < count; ++i) {
-        skew_evd_info one;
-        int rc = skew_evd_ex(h, n[i], A[i], lda[i], nev[i], lambda[i], Z_re[i], std::max(1, n[i]), Z_im[i],
-                             std::max(1, n[i]), opts, &one);
-        status[i] = rc;
-        if (rc && !first) first = rc;
-        acc.ms_total += one.ms_total;
-        for (int s = 0; s < 8; ++s) acc.ms_stage[s] += one.ms_stage[s];
-        acc.band = one.band;
+    if (info) memset(info, 0, sizeof(*info));
+    if (count == 0) return SKEW_EVD_OK;
+    // Problems are dealt to NS sub-handles (own stream and workspace), largest
+    // first to the least-loaded one (longest-processing-time rule, work ~ n^3);
+    // each sub-handle is driven by its own host thread, so the small solves
+    // overlap on the device.
+    // concurrent streams only for small problems: their cooperative launches
+    // (at most (n/b)/3 + 16 workgroups each) then fit on the device together
+    int nmax = 0;
+    for (int i = 0; i < count; ++i) nmax = std::max(nmax, n[i]);
+    const int NS = nmax <= 2048 ? std::min(count, 8) : 1;
+    while ((int)h->sub.size() < NS) {
+        hipStream_t s2;
+        HCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        skew_evd_handle sh = nullptr;
+        int rc = skew_evd_create(&sh, (void *)s2);
+        if (rc) {
+            (void)hipStreamDestroy(s2);
+            return rc;
+        }
+        h->sub.push_back(sh);
+        h->sub_streams.push_back(s2);
     }
-    acc.workspace_bytes = h->ws_bytes;
-    if (info) *info = acc;
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    std::vector<std::vector<int>> part(NS);
+    std::vector<double> load(NS, 0.0);
+    for (int i : order) {
+        int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        part[best].push_back(i);
+        load[best] += (double)n[i] * n[i] * n[i] + 1e6;
+    }
+    // the sub-streams start after the work already queued on h->stream
+    hipEvent_t start;
+    HCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    HCHK(hipEventRecord(start, h->stream));
+    for (int s2 = 0; s2 < NS; ++s2) HCHK(hipStreamWaitEvent(h->sub_streams[s2], start, 0));
+    std::vector<skew_evd_info> sinfo(NS);
+    std::vector<std::thread> workers;
+    for (int s2 = 0; s2 < NS; ++s2) {
+        workers.emplace_back([&, s2]() {
+            memset(&sinfo[s2], 0, sizeof(skew_evd_info));
+            for (int i : part[s2]) {
+                skew_evd_info one;
+                status[i] = skew_evd_ex(h->sub[s2], n[i], A[i], lda[i], nev[i], lambda[i], Z_re[i], std::max(1, n[i]),
+                                        Z_im[i], std::max(1, n[i]), opts, &one);
+                sinfo[s2].ms_total += one.ms_total;
+                for (int k = 0; k < 8; ++k) sinfo[s2].ms_stage[k] += one.ms_stage[k];
+                sinfo[s2].band = one.band;
+            }
+        });
+    }
+    for (auto &w : workers) w.join();
+    (void)hipEventDestroy(start);
+    int first = 0;
+    for (int i = 0; i < count; ++i)
+        if (status[i] && !first) first = status[i];
+    if (info) {
+        for (int s2 = 0; s2 < NS; ++s2) {
+            info->ms_total = std::max(info->ms_total, sinfo[s2].ms_total);
+            for (int k = 0; k < 8; ++k) info->ms_stage[k] += sinfo[s2].ms_stage[k];
+        }
+        size_t ws = 0;
+        for (auto sh : h->sub) ws += sh->ws_bytes;
+        info->workspace_bytes = ws;
+        info->band = sinfo[0].band;
+    }
     return first;
 }
 
@@ -534,6 +800,7 @@ int skew_evd_band_reduce(skew_evd_handle h, int n, const double *A, int lda, int
     if (n == 0) return SKEW_EVD_OK;
     Plan p = make_plan(n, 0, b, 0);
     Layout L = plan_layout(p);
+    kt_reset(h, false);
     int rc = ensure_ws(h, L.total, 0);
     if (rc) return rc;
     HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, h->stream));
@@ -556,6 +823,7 @@ int skew_evd_tridiagonalize(skew_evd_handle h, int n, const double *A, int lda, 
     if (n <= 1) return SKEW_EVD_OK;
     Plan p = make_plan(n, 0, b, 0);
     Layout L = plan_layout(p);
+    kt_reset(h, false);
     int rc = ensure_ws(h, L.total, 0);
     if (rc) return rc;
     HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, h->stream));
@@ -584,6 +852,7 @@ int skew_evd_tridiag_eig(skew_evd_handle h, int n, const double *alpha, int nev,
     p.ngroups = 0;
     p.nsig = 0;
     Layout L = plan_layout(p);
+    kt_reset(h, false);
     int rc = ensure_ws(h, L.total, 0);
     if (rc) return rc;
     HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, h->stream));

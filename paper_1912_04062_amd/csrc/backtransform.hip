@@ -86,23 +86,24 @@ __global__ __launch_bounds__(256) void k_bt2_tfac(const double *__restrict__ V2,
     }
 }
 
-// Stage-2 application.  Z is n x ncols (column-major, ldz).  NC = 32 columns
-// per workgroup.  LDS: Zs[128][NC+1], Vs[b][nb2] (+1), W1/W2 [64][NC+1].
+// Stage-2 application.  Z is n x ncols (column-major, ldz).  A workgroup owns
+// NCT = 64 columns, processed as two halves of 32 that share the group's V and
+// T staged in LDS.  LDS: Zs[128][33], Vs[b][nb2] and Ts[nb2][nb2] (ld 65),
+// W1/W2 [64][33].
 template <typename T>
 __global__ __launch_bounds__(256) void k_bt2_apply(T *__restrict__ Z, int ldz, int n, int ncols, int b, int nb2,
                                                    const T *__restrict__ V2, const T *__restrict__ T2,
                                                    const int *__restrict__ goff, int nsig)
 {
-    constexpr int NC = 32, LDZ = NC + 1, LDV = 65;
+    constexpr int NC = 32, NCT = 64, LDZ = NC + 1, LDV = 65;
     __shared__ T Zs[128 * LDZ];
     __shared__ T Vs[64 * LDV];
+    __shared__ T Ts[64 * LDV];
     __shared__ T W1[64 * LDZ];
     __shared__ T W2[64 * LDZ];
     typedef typename acc4<T>::type A4;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int col0 = blockIdx.x * NC;
-    const int ncl = min(NC, ncols - col0);
     const int Lmax = b + nb2 - 1;
 
     for (int sg = nsig - 1; sg >= 0; --sg) {
@@ -112,86 +113,97 @@ __global__ __launch_bounds__(256) void k_bt2_apply(T *__restrict__ Z, int ldz, i
             const int base = sg * nb2 + 1 + k * b;
             if (base >= n) break;
             const int L = min(Lmax, n - base);
-            // load Z rows and V
-            for (int e = tid; e < 128 * NC; e += 256) {
-                int r = e % 128, c = e / 128;
-                Zs[r * LDZ + c] = (r < L && c < ncl) ? Z[(size_t)(col0 + c) * ldz + base + r] : T(0);
-            }
             const T *Vg = V2 + (size_t)g * b * nb2;
+            const T *Tg = T2 + (size_t)g * nb2 * nb2;
+            __syncthreads();
             for (int e = tid; e < b * nb2; e += 256) {
                 int r = e % b, i = e / b;
                 Vs[r * LDV + i] = Vg[e];
             }
-            __syncthreads();
-            // W1 = Vpar^T Zs   (nb2 x NC); wave wv -> rows i in [16wv, 16wv+16)
-            if (16 * wv < nb2) {
-                A4 acc0 = (A4)(T(0)), acc1 = (A4)(T(0));
-                const int i = 16 * wv + lr;
-                const int rbeg = 16 * wv, rend = min(16 * wv + 16 + b - 1, 128);
-                for (int r4 = rbeg; r4 < rend; r4 += 4) {
-                    const int r = r4 + lk;
-                    const int d = r - i;
-                    T a = (i < nb2 && d >= 0 && d < b) ? Vs[d * LDV + i] : T(0);
-                    T b0 = Zs[r * LDZ + lr], b1 = Zs[r * LDZ + 16 + lr];
-                    acc0 = mfma_16x16x4(a, b0, acc0);
-                    acc1 = mfma_16x16x4(a, b1, acc1);
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int row = 16 * wv + mfma_row<T>(lane, q);
-                    W1[row * LDZ + lr] = acc0[q];
-                    W1[row * LDZ + 16 + lr] = acc1[q];
-                }
+            for (int e = tid; e < nb2 * nb2; e += 256) {
+                int i = e % nb2, u = e / nb2;
+                Ts[u * LDV + i] = Tg[e];          // Ts[u][i] = T[i][u]
             }
-            __syncthreads();
-            // W2 = T W1 (T upper, nb2 x nb2, from global)
-            if (16 * wv < nb2) {
-                A4 acc0 = (A4)(T(0)), acc1 = (A4)(T(0));
-                const int i = 16 * wv + lr;
-                const T *Tg = T2 + (size_t)g * nb2 * nb2;
-                for (int u4 = 16 * wv; u4 < nb2; u4 += 4) {
-                    const int u = u4 + lk;
-                    T a = (i < nb2 && u < nb2) ? Tg[(size_t)u * nb2 + i] : T(0);
-                    T b0 = (u < nb2) ? W1[u * LDZ + lr] : T(0);
-                    T b1 = (u < nb2) ? W1[u * LDZ + 16 + lr] : T(0);
-                    acc0 = mfma_16x16x4(a, b0, acc0);
-                    acc1 = mfma_16x16x4(a, b1, acc1);
+            for (int half = 0; half < NCT / NC; ++half) {
+                const int col0 = blockIdx.x * NCT + half * NC;
+                const int ncl = min(NC, ncols - col0);
+                if (ncl <= 0) break;
+                for (int e = tid; e < 128 * NC; e += 256) {
+                    int r = e % 128, c = e / 128;
+                    Zs[r * LDZ + c] = (r < L && c < ncl) ? Z[(size_t)(col0 + c) * ldz + base + r] : T(0);
                 }
+                __syncthreads();
+                // W1 = Vpar^T Zs   (nb2 x NC); wave wv -> rows i in [16wv, 16wv+16)
+                if (16 * wv < nb2) {
+                    A4 acc0 = (A4)(T(0)), acc1 = (A4)(T(0));
+                    const int i = 16 * wv + lr;
+                    const int rbeg = 16 * wv, rend = min(16 * wv + 16 + b - 1, 128);
+                    for (int r4 = rbeg; r4 < rend; r4 += 4) {
+                        const int r = r4 + lk;
+                        const int d = r - i;
+                        T a = (i < nb2 && d >= 0 && d < b) ? Vs[d * LDV + i] : T(0);
+                        T b0 = Zs[r * LDZ + lr], b1 = Zs[r * LDZ + 16 + lr];
+                        acc0 = mfma_16x16x4(a, b0, acc0);
+                        acc1 = mfma_16x16x4(a, b1, acc1);
+                    }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int row = 16 * wv + mfma_row<T>(lane, q);
-                    W2[row * LDZ + lr] = acc0[q];
-                    W2[row * LDZ + 16 + lr] = acc1[q];
-                }
-            }
-            __syncthreads();
-            // Z rows -= Vpar W2 ; row tiles mt = wv, wv+4 (128 rows = 8 tiles)
-            for (int mt = wv; mt < 8; mt += 4) {
-                if (16 * mt >= L) continue;
-                A4 acc0 = (A4)(T(0)), acc1 = (A4)(T(0));
-                const int r = 16 * mt + lr;
-                int ibeg = max(0, 16 * mt - b + 1) & ~3;
-                int iend = min(nb2, 16 * mt + 16);
-                for (int i4 = ibeg; i4 < iend; i4 += 4) {
-                    const int i = i4 + lk;
-                    const int d = r - i;
-                    T a = (i < nb2 && d >= 0 && d < b) ? Vs[d * LDV + i] : T(0);
-                    T b0 = (i < nb2) ? W2[i * LDZ + lr] : T(0);
-                    T b1 = (i < nb2) ? W2[i * LDZ + 16 + lr] : T(0);
-                    acc0 = mfma_16x16x4(a, b0, acc0);
-                    acc1 = mfma_16x16x4(a, b1, acc1);
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int row = 16 * mt + mfma_row<T>(lane, q);
-                    if (row < L) {
-                        if (lr < ncl) Z[(size_t)(col0 + lr) * ldz + base + row] = Zs[row * LDZ + lr] - acc0[q];
-                        if (16 + lr < ncl)
-                            Z[(size_t)(col0 + 16 + lr) * ldz + base + row] = Zs[row * LDZ + 16 + lr] - acc1[q];
+                    for (int q = 0; q < 4; ++q) {
+                        int row = 16 * wv + mfma_row<T>(lane, q);
+                        W1[row * LDZ + lr] = acc0[q];
+                        W1[row * LDZ + 16 + lr] = acc1[q];
                     }
                 }
+                __syncthreads();
+                // W2 = T W1 (T upper triangular)
+                if (16 * wv < nb2) {
+                    A4 acc0 = (A4)(T(0)), acc1 = (A4)(T(0));
+                    const int i = 16 * wv + lr;
+                    for (int u4 = 16 * wv; u4 < nb2; u4 += 4) {
+                        const int u = u4 + lk;
+                        T a = (i < nb2 && u < nb2) ? Ts[u * LDV + i] : T(0);
+                        T b0 = (u < nb2) ? W1[u * LDZ + lr] : T(0);
+                        T b1 = (u < nb2) ? W1[u * LDZ + 16 + lr] : T(0);
+                        acc0 = mfma_16x16x4(a, b0, acc0);
+                        acc1 = mfma_16x16x4(a, b1, acc1);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        int row = 16 * wv + mfma_row<T>(lane, q);
+                        W2[row * LDZ + lr] = acc0[q];
+                        W2[row * LDZ + 16 + lr] = acc1[q];
+                    }
+                }
+                __syncthreads();
+                // Zs -= Vpar W2 ; row tiles mt = wv, wv+4 (128 rows = 8 tiles)
+                for (int mt = wv; mt < 8; mt += 4) {
+                    if (16 * mt >= L) continue;
+                    A4 acc0 = (A4)(T(0)), acc1 = (A4)(T(0));
+                    const int r = 16 * mt + lr;
+                    int ibeg = max(0, 16 * mt - b + 1) & ~3;
+                    int iend = min(nb2, 16 * mt + 16);
+                    for (int i4 = ibeg; i4 < iend; i4 += 4) {
+                        const int i = i4 + lk;
+                        const int d = r - i;
+                        T a = (i < nb2 && d >= 0 && d < b) ? Vs[d * LDV + i] : T(0);
+                        T b0 = (i < nb2) ? W2[i * LDZ + lr] : T(0);
+                        T b1 = (i < nb2) ? W2[i * LDZ + 16 + lr] : T(0);
+                        acc0 = mfma_16x16x4(a, b0, acc0);
+                        acc1 = mfma_16x16x4(a, b1, acc1);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        int row = 16 * mt + mfma_row<T>(lane, q);
+                        Zs[row * LDZ + lr] -= acc0[q];
+                        Zs[row * LDZ + 16 + lr] -= acc1[q];
+                    }
+                }
+                __syncthreads();
+                for (int e = tid; e < 128 * NC; e += 256) {
+                    int r = e % 128, c = e / 128;
+                    if (r < L && c < ncl) Z[(size_t)(col0 + c) * ldz + base + r] = Zs[r * LDZ + c];
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 }
@@ -212,7 +224,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn_part(const T *__restrict__ A, i
     acc.zero();
     gemm::kloop<T, TM, TN, true, true>(fa, fb, m0, n0, kb, ke, smem, acc);
     double *C = Cpart + (size_t)s * M * N;
-    gemm::epilogue<T, TM, TN>(acc, [=](int i, int j, T v) {
+    gemm::epilogue<T, TM, TN>(acc, smem, [=](int i, int j, T v) {
         if (m0 + i < M && n0 + j < N) C[(size_t)(n0 + j) * M + m0 + i] = (double)v;
     });
 }
@@ -238,7 +250,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int ld
     gemm::Acc<T, TM, TN> acc;
     acc.zero();
     gemm::kloop<T, TM, TN, false, true>(fa, fb, m0, n0, 0, K, smem, acc);
-    gemm::epilogue<T, TM, TN>(acc, [=](int i, int j, T v) {
+    gemm::epilogue<T, TM, TN>(acc, smem, [=](int i, int j, T v) {
         int gi = m0 + i, gj = n0 + j;
         if (gi < M && gj < N) {
             T *p = C + (size_t)gj * ldc + gi;
@@ -310,7 +322,7 @@ void launch_bt2(T *Z, int ldz, int n, int ncols, int b, int nb2, const double *V
     if (ngroups <= 0 || ncols <= 0) return;
     hipLaunchKernelGGL(k_bt2_tfac<T>, dim3(ngroups), dim3(256), 0, st, V2, tau2, b, nb2, T2, V2t);
     const T *Vuse = V2t ? (const T *)V2t : (const T *)(const void *)V2;
-    hipLaunchKernelGGL(k_bt2_apply<T>, dim3(cdiv(ncols, 32)), dim3(256), 0, st, Z, ldz, n, ncols, b, nb2, Vuse,
+    hipLaunchKernelGGL(k_bt2_apply<T>, dim3(cdiv(ncols, 64)), dim3(256), 0, st, Z, ldz, n, ncols, b, nb2, Vuse,
                        (const T *)T2, goff_dev, nsig);
 }
 

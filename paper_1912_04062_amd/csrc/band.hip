@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_skew_symm(const T *__restrict__ W, int 
         __syncthreads();
     }
     T *Y = Ypart + (size_t)s * m * B;
-    gemm::epilogue<T, TM, TN>(acc, [=](int i, int j, T v) {
+    gemm::epilogue<T, TM, TN>(acc, smem, [=](int i, int j, T v) {
         if (m0 + i < m && j < B) Y[(size_t)j * m + m0 + i] = v;
     });
 }
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_gram(const T *__restrict__ Vd, const T 
     acc.zero();
     gemm::kloop<T, TB, TB, true, true>(fa, fb, 0, 0, kb, ke, smem, acc);
     double *G = Gp + (size_t)blockIdx.x * B * B;
-    gemm::epilogue<T, TB, TB>(acc, [=](int i, int j, T v) {
+    gemm::epilogue<T, TB, TB>(acc, smem, [=](int i, int j, T v) {
         if (i < B && j < B) G[(size_t)j * B + i] = (double)v;
     });
 }
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void k_wform(const T *__restrict__ Y0, const T
     gemm::Acc<T, TM, TN> acc;
     acc.zero();
     gemm::kloop<T, TM, TN, false, true>(fa, fb, m0, 0, 0, 2 * B, smem, acc);
-    gemm::epilogue<T, TM, TN>(acc, [=](int i, int j, T v) {
+    gemm::epilogue<T, TM, TN>(acc, smem, [=](int i, int j, T v) {
         if (m0 + i < m && j < B) Wd[(size_t)j * m + m0 + i] = v;
     });
 }
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_skew_syr2k(T *__restrict__ W, int ldw, 
     gemm::kloop<T, TT, TT, false, false>(fa, fb, m0, n0, 0, 2 * B, smem, acc);
     T *A0 = W + (size_t)r0 * ldw + r0;
     const bool diag = (I == J);
-    gemm::epilogue<T, TT, TT>(acc, [=](int i, int j, T v) {
+    gemm::epilogue<T, TT, TT>(acc, smem, [=](int i, int j, T v) {
         int gi = m0 + i, gj = n0 + j;
         if (gi < m && gj < m && (!diag || i > j)) A0[(size_t)gj * ldw + gi] += v;
     });
@@ -418,8 +418,8 @@ int symm_kchunk(int m, int S) { return (int)(cdiv(cdiv(m, S), 16) * 16); }
 int gram_chunk_rows() { return 512; }
 
 template <typename T>
-void launch_stage1_update(T *W, int ldw, int r0, int m, int B, const T *Vd, const double *Tf, T *Ypart,
-                          T *Y0, T *Wd, double *Gp, T *Tx, hipStream_t st)
+void launch_stage1_w(T *W, int ldw, int r0, int m, int B, const T *Vd, const double *Tf, T *Ypart,
+                     T *Y0, T *Wd, double *Gp, T *Tx, hipStream_t st)
 {
     const int S = symm_splits(m);
     const int kc = symm_kchunk(m, S);
@@ -450,6 +450,11 @@ void launch_stage1_update(T *W, int ldw, int r0, int m, int B, const T *Vd, cons
     else
         hipLaunchKernelGGL((k_wform<T, 32>), dim3(cdiv(m, 64)), dim3(256), (gemm::smem_bytes<T, 64, 32>()), st,
                            (const T *)Y0, Vd, (const T *)Tx, m, B, Wd);
+}
+
+template <typename T>
+void launch_stage1_syr2k(T *W, int ldw, int r0, int m, int B, const T *Vd, const T *Wd, hipStream_t st)
+{
     const int TT = 64;
     unsigned nt = cdiv(m, TT);
     unsigned ntiles = nt * (nt + 1) / 2;
@@ -471,10 +476,14 @@ template hipError_t launch_panel_qr<double>(double *, int, int, int, int, int, d
                                             double *, unsigned *, unsigned, unsigned *, hipStream_t);
 template hipError_t launch_panel_qr<float>(float *, int, int, int, int, int, float *, double *, double *,
                                            double *, unsigned *, unsigned, unsigned *, hipStream_t);
-template void launch_stage1_update<double>(double *, int, int, int, int, const double *, const double *,
-                                           double *, double *, double *, double *, double *, hipStream_t);
-template void launch_stage1_update<float>(float *, int, int, int, int, const float *, const double *,
-                                          float *, float *, float *, double *, float *, hipStream_t);
+template void launch_stage1_w<double>(double *, int, int, int, int, const double *, const double *, double *,
+                                      double *, double *, double *, double *, hipStream_t);
+template void launch_stage1_w<float>(float *, int, int, int, int, const float *, const double *, float *,
+                                     float *, float *, double *, float *, hipStream_t);
+template void launch_stage1_syr2k<double>(double *, int, int, int, int, const double *, const double *,
+                                          hipStream_t);
+template void launch_stage1_syr2k<float>(float *, int, int, int, int, const float *, const float *,
+                                         hipStream_t);
 template void launch_band_extract<double>(const double *, int, int, int, double *, int, hipStream_t);
 template void launch_band_extract<float>(const float *, int, int, int, double *, int, hipStream_t);
 

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 if (tid == 0) {
                     unsigned need = (unsigned)min(k + 3, nprev);
                     unsigned spins = 0;
-                    while (ld_acquire(&progress[s - 1]) < need) {
+                    while (ld_relaxed(&progress[s - 1]) < need) {
                         __builtin_amdgcn_s_sleep(1);
                         if (++spins > SKEW_SPIN_LIMIT) {
                             atomicOr(err, 2u);
@@ -68,6 +68,7 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                             break;
                         }
                     }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 __syncthreads();
                 if (abort_flag) return;
@@ -196,7 +197,10 @@ int chase_ngroups(int n, int b, int nb2, int *goff_host)
     return tot;
 }
 
-int chase_workgroups(int n)
+// Workgroups of the cooperative bulge-chase launch: enough for the sweeps
+// that can be in flight at once (a sweep of n/b steps starts every third
+// step of its predecessor), never more than the device holds.
+int chase_workgroups(int n, int b)
 {
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
@@ -205,6 +209,8 @@ int chase_workgroups(int n)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_bulge_chase, 256, 0);
     if (occ < 1) occ = 1;
     int G = ncu * occ;
+    const int inflight = (n / (b > 0 ? b : 1)) / 3 + 16;
+    if (G > inflight) G = inflight;
     if (G > n - 2) G = n - 2;
     if (G < 1) G = 1;
     return G;
@@ -214,7 +220,7 @@ hipError_t launch_chase(double *ab, int ldab, int n, int b, int nb2, double *V2,
                         const int *goff, unsigned *progress, unsigned *err, double *alpha, hipStream_t st)
 {
     if (n >= 3) {
-        int G = chase_workgroups(n);
+        int G = chase_workgroups(n, b);
         void *args[] = {&ab, &ldab, &n, &b, &nb2, &V2, &tau2, &goff, &progress, &err};
         hipError_t e = hipLaunchCooperativeKernel((const void *)k_bulge_chase, dim3(G), dim3(256), args, 0, st);
         if (e != hipSuccess) return e;

@@ -37,6 +37,10 @@ __device__ __forceinline__ unsigned ld_acquire(const unsigned *p)
 {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned ld_relaxed(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void st_release(unsigned *p, unsigned v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -58,7 +62,9 @@ __device__ __forceinline__ bool grid_sync(unsigned *ctr, unsigned target, unsign
         add_release(ctr, 1u);
         unsigned spins = 0;
         int ok = 1;
-        while (ld_acquire(ctr) < target) {
+        // spin with relaxed loads (an acquire load would invalidate caches on
+        // every iteration); one acquire fence once the count is reached
+        while (ld_relaxed(ctr) < target) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins > SKEW_SPIN_LIMIT) {
                 atomicOr(err, 1u);
@@ -66,6 +72,7 @@ __device__ __forceinline__ bool grid_sync(unsigned *ctr, unsigned target, unsign
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         gs_ok = ok;
     }
     __syncthreads();

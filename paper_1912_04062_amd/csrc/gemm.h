@@ -81,19 +81,37 @@ __device__ __forceinline__ void mma_chunk(const T *As, const T *Bs, Acc<T, TM, T
 }
 
 // Visit the tile's results: epi(row, col, value) with row/col relative to the
-// tile origin.
+// tile origin.  The tile is staged through LDS (smem, 32 columns at a time) so
+// that consecutive threads visit consecutive rows: column-major destinations
+// are then written with coalesced accesses.  Must be called by all threads.
 template <typename T, int TM, int TN, class E>
-__device__ __forceinline__ void epilogue(const Acc<T, TM, TN> &acc, const E &epi)
+__device__ __forceinline__ void epilogue(const Acc<T, TM, TN> &acc, T *smem, const E &epi)
 {
+    constexpr int LDC = TM + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm0 = (w >> 1) * (TM / 2), wn0 = (w & 1) * (TN / 2);
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < TM / 32; ++i)
+    for (int cb = 0; cb < TN / 32; ++cb) {
+        // columns [32 cb, 32 cb + 32): held by the waves with wn0 <= 32 cb < wn0 + TN/2
 #pragma unroll
-        for (int j = 0; j < TN / 32; ++j)
+        for (int i = 0; i < TM / 32; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                epi(wm0 + i * 16 + mfma_row<T>(lane, r), wn0 + j * 16 + (lane & 15), acc.v[i][j][r]);
+            for (int j = 0; j < TN / 32; ++j) {
+                const int c0 = wn0 + j * 16;
+                if (c0 >= 32 * cb && c0 < 32 * cb + 32)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        smem[(c0 - 32 * cb + (lane & 15)) * LDC + wm0 + i * 16 + mfma_row<T>(lane, r)] =
+                            acc.v[i][j][r];
+            }
+        __syncthreads();
+        for (int e = threadIdx.x; e < TM * 32; e += NT) {
+            const int r = e % TM, c = e / TM;
+            epi(r, 32 * cb + c, smem[c * LDC + r]);
+        }
+        __syncthreads();
+    }
 }
 
 // Full K loop: acc += sum_{k in [kb, ke)} A(m0 + i, k) B(k, n0 + j).
@@ -115,7 +133,9 @@ __device__ __forceinline__ void kloop(const FA &fa, const FB &fb, int m0, int n0
 
 template <typename T, int TM, int TN> __host__ __device__ constexpr size_t smem_bytes()
 {
-    return sizeof(T) * (size_t)(TK * (TM + 1) + TK * (TN + 1));
+    size_t ops = (size_t)(TK * (TM + 1) + TK * (TN + 1));
+    size_t epi = (size_t)32 * (TM + 1);
+    return sizeof(T) * (ops > epi ? ops : epi);
 }
 
 }  // namespace gemm

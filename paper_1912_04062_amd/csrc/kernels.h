@@ -18,8 +18,10 @@ int symm_splits(int m);
 int symm_kchunk(int m, int S);
 int gram_chunk_rows();
 template <typename T>
-void launch_stage1_update(T *W, int ldw, int r0, int m, int B, const T *Vd, const double *Tf, T *Ypart,
-                          T *Y0, T *Wd, double *Gp, T *Tx, hipStream_t st);
+void launch_stage1_w(T *W, int ldw, int r0, int m, int B, const T *Vd, const double *Tf, T *Ypart,
+                     T *Y0, T *Wd, double *Gp, T *Tx, hipStream_t st);
+template <typename T>
+void launch_stage1_syr2k(T *W, int ldw, int r0, int m, int B, const T *Vd, const T *Wd, hipStream_t st);
 template <typename T>
 void launch_band_extract(const T *W, int ldw, int n, int b, double *ab, int ldab, hipStream_t st);
 
@@ -55,5 +57,17 @@ template <typename T>
 void launch_copy_cols(const T *src, int lds, T *dst, int ldd, int m, int ncol, hipStream_t st);
 template <typename T>
 void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int ncol, hipStream_t st);
+
+// refine.hip
+template <typename T>
+void launch_build_x(const T *Z, int ldz, int n, int nev, int odd, double *X, hipStream_t st);
+void launch_split_x(const double *X, int n, int nev, int odd, double *Zr, int ldr, double *Zi, int ldi,
+                    hipStream_t st);
+void launch_refine_products(const double *A, int lda, int n, const double *X, int ncx, double *P, double *S,
+                            double *G, hipStream_t st);
+void launch_refine_eigs(const double *S, const double *G, int ncx, int nblk, int odd, double *lam, double *stat,
+                        hipStream_t st);
+void launch_refine_update(const double *S, const double *G, int n, int ncx, int nblk, int odd, const double *lam,
+                          double omega, float *E, const double *X, double *Xn, hipStream_t st);
 
 }  // namespace skew

@@ -99,7 +99,9 @@ __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, i
         hi = nhi;
     }
     if (active && q == 0) {
-        double lam = 0.5 * (lo + hi);
+        // the requested indices are the upper half of a spectrum symmetric
+        // about 0, so lambda >= 0; a midpoint may land a rounding error below
+        double lam = fmax(0.5 * (lo + hi), 0.0);
         if ((n & 1) && idx == n / 2) lam = 0.0;
         w[e] = lam;
     }

@@ -29,21 +29,35 @@ _PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32_REFINE, "fp32_refine": PREC_FP32_R
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("band", ctypes.c_int),
                 ("max_refine_sweeps", ctypes.c_int), ("refine_tol", ctypes.c_double),
-                ("workspace_limit", ctypes.c_size_t), ("reserved", ctypes.c_int * 8)]
+                ("workspace_limit", ctypes.c_size_t), ("profile", ctypes.c_int),
+                ("reserved", ctypes.c_int * 7)]
+
+
+class KStat(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("launches", ctypes.c_int), ("bound", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_double), ("ms_stage", ctypes.c_double * 8),
                 ("band", ctypes.c_int), ("refine_sweeps", ctypes.c_int),
-                ("refine_residual", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t)]
+                ("refine_residual", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
+                ("kern", KStat * 8)]
 
     STAGES = ("ingest", "full_to_band", "bulge_chase", "tridiag_solve", "bt2", "bt1",
               "refine", "copy_out")
+    KERNELS = ("panel_qr", "skew_symm_w", "skew_syr2k", "bulge_chase", "tridiag", "bt2", "bt1",
+               "refine")
+    BOUNDS = ("mfma", "hbm", "alu")
 
     def as_dict(self):
         d = {"ms_total": self.ms_total, "band": self.band, "refine_sweeps": self.refine_sweeps,
              "refine_residual": self.refine_residual, "workspace_bytes": int(self.workspace_bytes)}
         d["ms_stage"] = {k: self.ms_stage[i] for i, k in enumerate(self.STAGES)}
+        d["kernels"] = {k: {"ms": self.kern[i].ms, "flops": self.kern[i].flops,
+                            "bytes": self.kern[i].bytes, "launches": self.kern[i].launches,
+                            "bound": self.BOUNDS[self.kern[i].bound]}
+                        for i, k in enumerate(self.KERNELS)}
         return d
 
 
@@ -102,7 +116,7 @@ def status_string(status):
 
 
 def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=None,
-                 workspace_limit=0):
+                 workspace_limit=0, profile=0):
     o = Opts()
     _load().skew_evd_default_opts(ctypes.byref(o))
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
@@ -112,6 +126,7 @@ def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=No
     if refine_tol is not None:
         o.refine_tol = float(refine_tol)
     o.workspace_limit = int(workspace_limit)
+    o.profile = int(profile)
     return o
 
 
@@ -156,7 +171,7 @@ class Handle:
 
     # -- solver --------------------------------------------------------------
     def solve(self, A, nev=None, precision="fp64", band=0, opts=None, info=None, out=None,
-              check=True):
+              check=True, profile=0):
         """Eigenpairs of the skew-symmetric A (torch float64 CUDA tensor, n x n).
 
         Returns (lam, Zre, Zim): lam (nev,), Zre/Zim (n, nev) column-major
@@ -173,7 +188,7 @@ class Handle:
             zi = empty_colmajor(max(n, 1), max(nev, 1), dev)
         else:
             lam, zr, zi = out
-        o = opts if opts is not None else default_opts(precision, band)
+        o = opts if opts is not None else default_opts(precision, band, profile=profile)
         inf = info if info is not None else Info()
         st = self._lib.skew_evd_ex(self._h, n, ctypes.c_void_p(Ac.data_ptr()), lda, nev,
                                    ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(zr.data_ptr()),
