@@ -31,6 +31,7 @@ void set_hip_error(hipError_t e, const char *what)
     } while (0)
 
 constexpr int NSTAGE_EV = 9;
+constexpr int SKEW_EVD_REFINE_CLUSTER = 100;   // internal: refinement met unresolvable clusters
 constexpr int ORTH_NB = 64;
 
 struct Plan {
@@ -459,6 +460,9 @@ int validate_opts(const skew_evd_opts *o)
     return 0;
 }
 
+int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *lambda, double *Z_re, int ldzr,
+          double *Z_im, int ldzi, const skew_evd_opts *opts, skew_evd_info *info);
+
 // Precision form: refine the FP32 pipeline's eigenpairs against the FP64 A.
 // Returns OK or WARN_REFINE; results are written to lambda / Z_re / Z_im.
 int refine(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, int lda, const skew_evd_opts &o,
@@ -497,13 +501,23 @@ int refine(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, i
         }
         if (o.max_refine_sweeps == 0) break;
         const double omega = 64.0 * 2.220446049250313e-16 * lmax;
+        unsigned *nclust = (unsigned *)(stat + 4);
         skew::launch_refine_update(ptr<double>(h, L.rS), ptr<double>(h, L.rG), n, ncx, nblk, odd,
-                                   ptr<double>(h, L.rlam), omega, ptr<float>(h, L.rE), X, Xn, st);
+                                   ptr<double>(h, L.rlam), omega, ptr<float>(h, L.rE), X, Xn, nclust, st);
         HCHK(hipGetLastError());
+        unsigned hc = 0;
+        HCHK(hipMemcpyAsync(&hc, nclust, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+        if (hc) {
+            // near-degenerate pairs the FP32 start cannot separate: not refinable here
+            *sweeps_out = sweeps;
+            *res_out = last;
+            return SKEW_EVD_REFINE_CLUSTER;
+        }
         std::swap(X, Xn);
         ++sweeps;
         // a Newton step from a residual r leaves about r^2 (quadratic convergence)
-        if (last * last * 1e2 <= o.refine_tol) {
+        if (last * last <= o.refine_tol) {
             converged = true;
             break;
         }
@@ -554,6 +568,14 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     if (prec) {
         HCHK(kt_begin(h, SKEW_EVD_K_REFINE));
         refine_rc = refine(h, p, L, A, lda, o, nev_out, lambda, Z_re, ldzr, Z_im, ldzi, &rsweeps, &rres);
+        if (refine_rc == SKEW_EVD_REFINE_CLUSTER) {
+            // clusters closer than the FP32 pipeline resolves: fall back to the FP64 form
+            skew_evd_opts o64 = o;
+            o64.precision = SKEW_EVD_PREC_FP64;
+            int rc64 = solve(h, n, A, lda, nev_out, lambda, Z_re, ldzr, Z_im, ldzi, &o64, info);
+            if (info) info->refine_sweeps = -1;   // marks the fallback
+            return rc64;
+        }
         if (refine_rc != SKEW_EVD_OK && refine_rc != SKEW_EVD_WARN_REFINE) return refine_rc;
         HCHK(kt_end(h, SKEW_EVD_K_REFINE));
     }

@@ -250,14 +250,16 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int ld
     gemm::Acc<T, TM, TN> acc;
     acc.zero();
     gemm::kloop<T, TM, TN, false, true>(fa, fb, m0, n0, 0, K, smem, acc);
-    gemm::epilogue<T, TM, TN>(acc, smem, [=](int i, int j, T v) {
-        int gi = m0 + i, gj = n0 + j;
-        if (gi < M && gj < N) {
-            T *p = C + (size_t)gj * ldc + gi;
-            T r = (T)(alpha * (double)v);
-            *p = beta ? (T)(*p + r) : r;
-        }
-    });
+    gemm::epilogue_rmw<T, TM, TN>(
+        acc, smem,
+        [=](int i, int j) -> T {
+            const int gi = m0 + i, gj = n0 + j;
+            return (beta && gi < M && gj < N) ? C[(size_t)gj * ldc + gi] : T(0);
+        },
+        [=](int i, int j, T old, T v) {
+            const int gi = m0 + i, gj = n0 + j;
+            if (gi < M && gj < N) C[(size_t)gj * ldc + gi] = (T)((double)old + alpha * (double)v);
+        });
 }
 
 // out = S0 * sum_s Cpart[s]  (S0: M x M column-major, M <= 64) or, with

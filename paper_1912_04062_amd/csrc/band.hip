@@ -207,16 +207,7 @@ __global__ __launch_bounds__(256) void k_skew_symm(const T *__restrict__ W, int 
     };
     gemm::Acc<T, TM, TN> acc;
     acc.zero();
-    T *As = smem, *Bs = smem + gemm::TK * (TM + 1);
-    for (int k0 = kb; k0 < ke; k0 += gemm::TK) {
-        if (k0 + gemm::TK <= m0) gemm::fill<T, TM, false>(As, f_low, m0, k0);
-        else if (k0 >= m0 + TM) gemm::fill<T, TM, true>(As, f_up, m0, k0);
-        else gemm::fill<T, TM, false>(As, f_mix, m0, k0);
-        gemm::fill<T, TN, true>(Bs, f_v, 0, k0);
-        __syncthreads();
-        gemm::mma_chunk<T, TM, TN>(As, Bs, acc);
-        __syncthreads();
-    }
+    gemm::skew_kloop<T, TM, TN>(f_low, f_up, f_mix, f_v, m0, 0, kb, ke, smem, acc);
     T *Y = Ypart + (size_t)s * m * B;
     gemm::epilogue<T, TM, TN>(acc, smem, [=](int i, int j, T v) {
         if (m0 + i < m && j < B) Y[(size_t)j * m + m0 + i] = v;
@@ -338,10 +329,13 @@ __global__ __launch_bounds__(256) void k_skew_syr2k(T *__restrict__ W, int ldw, 
     gemm::kloop<T, TT, TT, false, false>(fa, fb, m0, n0, 0, 2 * B, smem, acc);
     T *A0 = W + (size_t)r0 * ldw + r0;
     const bool diag = (I == J);
-    gemm::epilogue<T, TT, TT>(acc, smem, [=](int i, int j, T v) {
-        int gi = m0 + i, gj = n0 + j;
-        if (gi < m && gj < m && (!diag || i > j)) A0[(size_t)gj * ldw + gi] += v;
-    });
+    auto inside = [=](int i, int j) { return m0 + i < m && n0 + j < m && (!diag || i > j); };
+    gemm::epilogue_rmw<T, TT, TT>(
+        acc, smem,
+        [=](int i, int j) -> T { return inside(i, j) ? A0[(size_t)(n0 + j) * ldw + m0 + i] : T(0); },
+        [=](int i, int j, T old, T v) {
+            if (inside(i, j)) A0[(size_t)(n0 + j) * ldw + m0 + i] = old + v;
+        });
 }
 
 template <typename T>

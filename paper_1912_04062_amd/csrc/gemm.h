@@ -114,7 +114,43 @@ __device__ __forceinline__ void epilogue(const Acc<T, TM, TN> &acc, T *smem, con
     }
 }
 
-// Full K loop: acc += sum_{k in [kb, ke)} A(m0 + i, k) B(k, n0 + j).
+// Global -> registers half of a fill (the chunk's elements owned by this
+// thread), and registers -> LDS half.  Splitting the two lets the K loop keep
+// the next chunk's global loads in flight while the MFMAs of the current one
+// run.
+template <typename T, int TX> struct Frag {
+    T v[TX * TK / NT];
+};
+
+template <typename T, int TX, bool KC, class F>
+__device__ __forceinline__ void gload(Frag<T, TX> &r, const F &f, int x0, int k0)
+{
+    constexpr int PER = TX * TK / NT;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = t + p * NT;
+        if constexpr (KC) r.v[p] = f(x0 + (e >> 4), k0 + (e & (TK - 1)));
+        else r.v[p] = f(x0 + e % TX, k0 + e / TX);
+    }
+}
+
+template <typename T, int TX, bool KC>
+__device__ __forceinline__ void lstore(T *L, const Frag<T, TX> &r)
+{
+    constexpr int LD = lds_ld<TX>();
+    constexpr int PER = TX * TK / NT;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = t + p * NT;
+        if constexpr (KC) L[(e & (TK - 1)) * LD + (e >> 4)] = r.v[p];
+        else L[(e / TX) * LD + e % TX] = r.v[p];
+    }
+}
+
+// Full K loop: acc += sum_{k in [kb, ke)} A(m0 + i, k) B(k, n0 + j), with the
+// next K-chunk prefetched into registers during the current chunk's MFMAs.
 // smem must hold 16*(TM+1) + 16*(TN+1) elements.
 template <typename T, int TM, int TN, bool AKC, bool BKC, class FA, class FB>
 __device__ __forceinline__ void kloop(const FA &fa, const FB &fb, int m0, int n0, int kb, int ke,
@@ -122,11 +158,98 @@ __device__ __forceinline__ void kloop(const FA &fa, const FB &fb, int m0, int n0
 {
     T *As = smem;
     T *Bs = smem + TK * lds_ld<TM>();
+    if (kb >= ke) return;
+    Frag<T, TM> ra;
+    Frag<T, TN> rb;
+    gload<T, TM, AKC>(ra, fa, m0, kb);
+    gload<T, TN, BKC>(rb, fb, n0, kb);
     for (int k0 = kb; k0 < ke; k0 += TK) {
-        fill<T, TM, AKC>(As, fa, m0, k0);
-        fill<T, TN, BKC>(Bs, fb, n0, k0);
+        lstore<T, TM, AKC>(As, ra);
+        lstore<T, TN, BKC>(Bs, rb);
         __syncthreads();
+        if (k0 + TK < ke) {
+            gload<T, TM, AKC>(ra, fa, m0, k0 + TK);
+            gload<T, TN, BKC>(rb, fb, n0, k0 + TK);
+        }
         mma_chunk<T, TM, TN>(As, Bs, acc);
+        __syncthreads();
+    }
+}
+
+// K loop whose A operand is a skew matrix read from its strict lower
+// triangle: chunks left of the tile's rows come from the lower triangle
+// (x-contiguous), chunks right of them from the transposed lower triangle
+// (k-contiguous, negated), the diagonal chunks element by element.
+template <typename T, int TM, int TN, class FL, class FU, class FM, class FB>
+__device__ __forceinline__ void skew_kloop(const FL &f_low, const FU &f_up, const FM &f_mix, const FB &fb, int m0,
+                                           int n0, int kb, int ke, T *smem, Acc<T, TM, TN> &acc)
+{
+    T *As = smem;
+    T *Bs = smem + TK * lds_ld<TM>();
+    if (kb >= ke) return;
+    auto mode_of = [&](int k0) { return (k0 + TK <= m0) ? 0 : ((k0 >= m0 + TM) ? 1 : 2); };
+    auto load_a = [&](Frag<T, TM> &r, int mode, int k0) {
+        if (mode == 0) gload<T, TM, false>(r, f_low, m0, k0);
+        else if (mode == 1) gload<T, TM, true>(r, f_up, m0, k0);
+        else gload<T, TM, false>(r, f_mix, m0, k0);
+    };
+    Frag<T, TM> ra;
+    Frag<T, TN> rb;
+    int mode = mode_of(kb);
+    load_a(ra, mode, kb);
+    gload<T, TN, true>(rb, fb, n0, kb);
+    for (int k0 = kb; k0 < ke; k0 += TK) {
+        if (mode == 1) lstore<T, TM, true>(As, ra);
+        else lstore<T, TM, false>(As, ra);
+        lstore<T, TN, true>(Bs, rb);
+        __syncthreads();
+        if (k0 + TK < ke) {
+            mode = mode_of(k0 + TK);
+            load_a(ra, mode, k0 + TK);
+            gload<T, TN, true>(rb, fb, n0, k0 + TK);
+        }
+        mma_chunk<T, TM, TN>(As, Bs, acc);
+        __syncthreads();
+    }
+}
+
+// Read-modify-write epilogue: ld(row, col) returns the destination's current
+// value (0 outside), st(row, col, old, acc) stores the combination.  All loads
+// of a column block are issued before its stores.
+template <typename T, int TM, int TN, class LD, class ST>
+__device__ __forceinline__ void epilogue_rmw(const Acc<T, TM, TN> &acc, T *smem, const LD &ld, const ST &st)
+{
+    constexpr int LDC = TM + 1;
+    constexpr int EPT = TM * 32 / NT;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm0 = (w >> 1) * (TM / 2), wn0 = (w & 1) * (TN / 2);
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < TN / 32; ++cb) {
+#pragma unroll
+        for (int i = 0; i < TM / 32; ++i)
+#pragma unroll
+            for (int j = 0; j < TN / 32; ++j) {
+                const int c0 = wn0 + j * 16;
+                if (c0 >= 32 * cb && c0 < 32 * cb + 32)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        smem[(c0 - 32 * cb + (lane & 15)) * LDC + wm0 + i * 16 + mfma_row<T>(lane, r)] =
+                            acc.v[i][j][r];
+            }
+        __syncthreads();
+        decltype(ld(0, 0)) old[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = threadIdx.x + q * NT;
+            old[q] = ld(e % TM, 32 * cb + e / TM);
+        }
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = threadIdx.x + q * NT;
+            const int r = e % TM, c = e / TM;
+            st(r, 32 * cb + c, old[q], smem[c * LDC + r]);
+        }
         __syncthreads();
     }
 }

@@ -74,16 +74,7 @@ __global__ __launch_bounds__(256) void k_skew_mm(const double *__restrict__ A, i
     auto f_x = [=](int j, int k) -> double { return (j < ncx && k < n) ? X[(size_t)j * n + k] : 0.0; };
     gemm::Acc<double, TM, TN> acc;
     acc.zero();
-    double *As = smem, *Bs = smem + gemm::TK * (TM + 1);
-    for (int k0 = 0; k0 < n; k0 += gemm::TK) {
-        if (k0 + gemm::TK <= m0) gemm::fill<double, TM, false>(As, f_low, m0, k0);
-        else if (k0 >= m0 + TM) gemm::fill<double, TM, true>(As, f_up, m0, k0);
-        else gemm::fill<double, TM, false>(As, f_mix, m0, k0);
-        gemm::fill<double, TN, true>(Bs, f_x, n0, k0);
-        __syncthreads();
-        gemm::mma_chunk<double, TM, TN>(As, Bs, acc);
-        __syncthreads();
-    }
+    gemm::skew_kloop<double, TM, TN>(f_low, f_up, f_mix, f_x, m0, n0, 0, n, smem, acc);
     gemm::epilogue<double, TM, TN>(acc, smem, [=](int i, int j, double v) {
         if (m0 + i < n && n0 + j < ncx) P[(size_t)(n0 + j) * n + m0 + i] = v;
     });
@@ -109,11 +100,20 @@ __global__ __launch_bounds__(256) void k_xtp_xtx(const double *__restrict__ X, c
     a1.zero();
     a2.zero();
     double *As = smem, *Bs = smem + gemm::TK * (TT + 1), *Cs = Bs + gemm::TK * (TT + 1);
+    gemm::Frag<double, TT> ra, rb, rc;
+    gemm::gload<double, TT, true>(ra, fa, m0, 0);
+    gemm::gload<double, TT, true>(rb, fp, n0, 0);
+    gemm::gload<double, TT, true>(rc, fx, n0, 0);
     for (int k0 = 0; k0 < n; k0 += gemm::TK) {
-        gemm::fill<double, TT, true>(As, fa, m0, k0);
-        gemm::fill<double, TT, true>(Bs, fp, n0, k0);
-        gemm::fill<double, TT, true>(Cs, fx, n0, k0);
+        gemm::lstore<double, TT, true>(As, ra);
+        gemm::lstore<double, TT, true>(Bs, rb);
+        gemm::lstore<double, TT, true>(Cs, rc);
         __syncthreads();
+        if (k0 + gemm::TK < n) {
+            gemm::gload<double, TT, true>(ra, fa, m0, k0 + gemm::TK);
+            gemm::gload<double, TT, true>(rb, fp, n0, k0 + gemm::TK);
+            gemm::gload<double, TT, true>(rc, fx, n0, k0 + gemm::TK);
+        }
         gemm::mma_chunk<double, TT, TT>(As, Bs, a1);
         gemm::mma_chunk<double, TT, TT>(As, Cs, a2);
         __syncthreads();
@@ -177,7 +177,7 @@ __global__ void k_stats(const double *__restrict__ S, const double *__restrict__
 // E (ncx x ncx, type TE): one thread per block pair (p, q).
 template <typename TE>
 __global__ void k_eform(const double *__restrict__ S, const double *__restrict__ G, int ncx, int nblk, int odd,
-                        const double *__restrict__ lam, double omega, TE *__restrict__ E)
+                        const double *__restrict__ lam, double omega, TE *__restrict__ E, unsigned *nclust)
 {
     const int p = blockIdx.x * 16 + threadIdx.x % 16;
     const int q = blockIdx.y * 16 + threadIdx.x / 16;
@@ -232,6 +232,19 @@ __global__ void k_eform(const double *__restrict__ S, const double *__restrict__
             e[1][0] = C[0][0] / a;
         }
     }
+    // a Newton step is only valid for small corrections: a pair whose solution
+    // is not small is near-degenerate at this accuracy; it keeps E = R/2 and is
+    // counted (the caller then solves the problem in FP64 instead)
+    if (p != q) {
+        double mx = 0.0;
+        for (int i = 0; i < sp; ++i)
+            for (int j = 0; j < sq; ++j) mx = fmax(mx, fabs(e[i][j]));
+        if (!(mx <= 0.25)) {
+            for (int i = 0; i < sp; ++i)
+                for (int j = 0; j < sq; ++j) e[i][j] = 0.5 * Rv(cp + i, cq + j);
+            atomicAdd(nclust, 1u);
+        }
+    }
     for (int i = 0; i < sp; ++i)
         for (int j = 0; j < sq; ++j) E[(size_t)(cq + j) * ncx + cp + i] = (TE)e[i][j];
 }
@@ -249,10 +262,17 @@ __global__ __launch_bounds__(256) void k_xe(const double *__restrict__ X, const 
     gemm::Acc<T, TM, TN> acc;
     acc.zero();
     gemm::kloop<T, TM, TN, false, true>(fa, fb, m0, n0, 0, ncx, smem, acc);
-    gemm::epilogue<T, TM, TN>(acc, smem, [=](int i, int j, T v) {
-        const int gi = m0 + i, gj = n0 + j;
-        if (gi < n && gj < ncx) Xn[(size_t)gj * n + gi] = X[(size_t)gj * n + gi] + (double)v;
-    });
+    // the old values come from X (double) and the result goes to Xn
+    gemm::epilogue_rmw<T, TM, TN>(
+        acc, smem,
+        [=](int i, int j) -> double {
+            const int gi = m0 + i, gj = n0 + j;
+            return (gi < n && gj < ncx) ? X[(size_t)gj * n + gi] : 0.0;
+        },
+        [=](int i, int j, double old, T v) {
+            const int gi = m0 + i, gj = n0 + j;
+            if (gi < n && gj < ncx) Xn[(size_t)gj * n + gi] = old + (double)v;
+        });
 }
 
 }  // namespace
@@ -297,10 +317,10 @@ void launch_refine_eigs(const double *S, const double *G, int ncx, int nblk, int
 }
 
 void launch_refine_update(const double *S, const double *G, int n, int ncx, int nblk, int odd, const double *lam,
-                          double omega, float *E, const double *X, double *Xn, hipStream_t st)
+                          double omega, float *E, const double *X, double *Xn, unsigned *nclust, hipStream_t st)
 {
     hipLaunchKernelGGL(k_eform<float>, dim3(cdiv(nblk, 16), cdiv(nblk, 16)), dim3(256), 0, st, S, G, ncx, nblk, odd,
-                       lam, omega, E);
+                       lam, omega, E, nclust);
     dim3 g(cdiv(n, 128), cdiv(ncx, 128));
     hipLaunchKernelGGL((k_xe<float, float, 128, 128>), g, dim3(256), (gemm::smem_bytes<float, 128, 128>()), st, X,
                        (const float *)E, n, ncx, Xn);
