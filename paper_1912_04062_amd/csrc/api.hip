@@ -71,7 +71,7 @@ namespace {
 struct Layout {
     size_t W, Vall, Tall, tauall, Ypart, Y0, Wd, Gp, Tx, part, ab, goff, V2, tau2, T2, V2t, alpha, a2, stats,
         lam, U0, U1, U2, Lm, Sw, Yiv, Qd, Z, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
-        rstat, total;
+        rstat, Tm, total;
     std::vector<size_t> Voff;
 };
 
@@ -100,6 +100,7 @@ Layout plan_layout(const Plan &p)
     }
     L.Vall = take(es * vtot);
     L.Tall = take(sizeof(double) * (size_t)std::max(p.npanels, 1) * b * b);
+    L.Tm = take(sizeof(double) * (size_t)(p.npanels / 2 + 1) * 4 * b * b);
     L.tauall = take(sizeof(double) * (size_t)std::max(p.npanels, 1) * b);
     const size_t m0 = n > b ? n - b : 1;
     L.Ypart = take(es * 16 * m0 * b);
@@ -412,6 +413,41 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L)
     HCHK(kt_end(h, SKEW_EVD_K_BT2));
     HCHK(hipGetLastError());
     HCHK(hipEventRecord(h->ev[5], st));
+    if (b == 64 || b == 32) {
+        // consecutive panels merged in pairs: Q_j Q_{j+1} = I - V T V^T with
+        // V = [V_j, V_{j+1} shifted by b rows]; pairs end at the last panel
+        const int P = p.npanels;
+        HCHK(kt_begin(h, SKEW_EVD_K_BT1));
+        int q = 0;
+        for (int j0 = P - 2; j0 >= 0; j0 -= 2, ++q) {
+            const int m0 = n - (j0 + 1) * b, m1 = m0 - b;
+            const T *V0 = ptr<T>(h, L.Vall) + L.Voff[j0];
+            const T *V1 = ptr<T>(h, L.Vall) + L.Voff[j0 + 1];
+            int S = skew::launch_gemm_tn_part<T>(V0 + b, m0, V1, m1, b, b, m1, ptr<double>(h, L.Wp), st);
+            skew::launch_merge_t(ptr<double>(h, L.Tall) + (size_t)j0 * b * b,
+                                 ptr<double>(h, L.Tall) + (size_t)(j0 + 1) * b * b, ptr<double>(h, L.Wp), S, b,
+                                 ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, st);
+            skew::launch_bt1_fused<T>(Z, n, (j0 + 1) * b, m0, 2 * nev, V0, b, V1, m1,
+                                      ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, 2 * b, st);
+            HCHK(hipGetLastError());
+        }
+        if (P % 2 == 1) {                    // panel 0 alone
+            const int m0 = n - b;
+            const T *V0 = ptr<T>(h, L.Vall) + L.Voff[0];
+            const double *Tf = ptr<double>(h, L.Tall);
+            if (b == 64) {
+                skew::launch_bt1_fused<T>(Z, n, b, m0, 2 * nev, V0, b, nullptr, 0, Tf, b, st);
+            } else {
+                int S = skew::launch_gemm_tn_part<T>(V0, m0, Z + b, n, b, 2 * nev, m0, ptr<double>(h, L.Wp), st);
+                skew::launch_reduce_left(Tf, ptr<double>(h, L.Wp), S, b, 2 * nev, ptr<double>(h, L.Wt2), st);
+                skew::launch_gemm_nn<T>(V0, m0, ptr<double>(h, L.Wt2), 1, m0, 2 * nev, b, Z + b, n, -1.0, 1, st);
+            }
+            HCHK(hipGetLastError());
+        }
+        HCHK(kt_end(h, SKEW_EVD_K_BT1));
+        HCHK(hipEventRecord(h->ev[6], st));
+        return SKEW_EVD_OK;
+    }
     for (int j = p.npanels - 1; j >= 0; --j) {
         const int r0 = (j + 1) * b, m = n - r0;
         const T *Vd = ptr<T>(h, L.Vall) + L.Voff[j];

@@ -208,6 +208,334 @@ __global__ __launch_bounds__(256) void k_bt2_apply(T *__restrict__ Z, int ldz, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// Stage-2 application, FP64, b = nb2 = 64: register-resident sliding window.
+//
+// Row block x = rows [1 + 64x, 1 + 64(x+1)).  Group (s, k) (sweep-block s,
+// step k) acts on row blocks t = s + k and t + 1.  Required order: (s, k)
+// before (s, k+1), and (s+1, k') before (s, k) when they share rows.  With two
+// sweep-blocks s_hi, s_hi - 1 per pass, the schedule tau(s, k) = k + (s_hi - s)
+// satisfies both, and the groups of one tau are row-disjoint; at time tau the
+// active row blocks are s_hi + tau - 2 .. s_hi + tau + 1, a window of 4 blocks
+// that slides down by one block per tau.  Z is therefore read and written once
+// per pass of two sweep-blocks.
+//
+// A workgroup owns 64 columns; each wavefront keeps its 16-column strip of the
+// 256-row window in registers, in the MFMA result layout (row 16q + l/16 + 4r
+// of tile q, column l%16).  For the FP64 16x16x4 MFMA that layout is also the
+// B-operand layout of k-step 4r of the tile, so Z, W1 = V^T Z and W2 = T W1
+// never leave registers; V (as a 128 x 64 parallelogram) and T are in LDS.
+namespace bt2w {
+
+constexpr int B = 64, LDP = 65;
+
+struct Win {
+    d4 z[4][4];      // [slot][row tile]
+};
+
+__device__ __forceinline__ bool blk_valid(int x, int n) { return x >= 0 && 1 + 64 * x < n; }
+
+// global rows of block x (64 x 64 of this workgroup's columns) -> slot, via LDS
+template <int SL>
+__device__ __forceinline__ void load_block(Win &w, const double *__restrict__ Z, int ldz, int n, int col0, int ncl,
+                                           int x, double *St)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __syncthreads();
+    const bool ok = blk_valid(x, n);
+    const int r0 = 1 + 64 * x;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        const int e = tid + 256 * p;
+        const int r = e & 63, c = e >> 6;
+        double v = 0.0;
+        if (ok && r0 + r < n && c < ncl) v = Z[(size_t)(col0 + c) * ldz + r0 + r];
+        St[r * LDP + c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+            w.z[SL][q][rr] = St[(16 * q + (lane >> 4) + 4 * rr) * LDP + 16 * wv + (lane & 15)];
+}
+
+template <int SL>
+__device__ __forceinline__ void store_block(const Win &w, double *__restrict__ Z, int ldz, int n, int col0, int ncl,
+                                            int x, double *St)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (!blk_valid(x, n)) return;            // uniform across the workgroup
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+            St[(16 * q + (lane >> 4) + 4 * rr) * LDP + 16 * wv + (lane & 15)] = w.z[SL][q][rr];
+    __syncthreads();
+    const int r0 = 1 + 64 * x;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        const int e = tid + 256 * p;
+        const int r = e & 63, c = e >> 6;
+        if (r0 + r < n && c < ncl) Z[(size_t)(col0 + c) * ldz + r0 + r] = St[r * LDP + c];
+    }
+}
+
+// Apply group g to the row blocks in slots S0 (upper) and S1 (lower).
+template <int S0, int S1>
+__device__ __forceinline__ void apply_group(Win &w, const double *__restrict__ V2, const double *__restrict__ T2,
+                                            size_t g, double *Vp, double *Ts)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    // parallelogram Vp[d + i][i] = V[d][i] (its zero part is set once per
+    // kernel) and Ts[u][i] = T[i][u]; all global loads issued first
+    const double *Vg = V2 + g * (size_t)(B * B);
+    const double *Tg = T2 + g * (size_t)(B * B);
+    double vv[16], tt[16];
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        const int e = tid + 256 * p;
+        vv[p] = Vg[e];
+        tt[p] = Tg[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        const int e = tid + 256 * p;
+        const int d = e & 63, i = e >> 6;       // V is column-major b x nb2
+        Vp[(d + i) * LDP + i] = vv[p];
+        Ts[(e >> 6) * LDP + (e & 63)] = tt[p];
+    }
+    __syncthreads();
+    // W1 = Vp^T Zg   (4 row tiles over i; K = 128 rows of the two slots)
+    d4 w1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 32; ++ks) {          // k-step over rows r4 = 4 ks
+            if (ks < 4 * mt || ks >= 4 * mt + 20) continue;   // outside the parallelogram
+            const int r4 = 4 * ks;
+            const double a = Vp[(r4 + lk) * LDP + 16 * mt + lr];
+            const int tile = ks >> 2, rr = ks & 3;   // tile of 16 rows within the 128
+            const double bz = (tile < 4) ? w.z[S0][tile & 3][rr] : w.z[S1][tile & 3][rr];
+            acc = mfma_16x16x4(a, bz, acc);
+        }
+        w1[mt] = acc;
+    }
+    // W2 = T W1   (T upper triangular)
+    d4 w2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            if (ks < 4 * mt) continue;
+            const double a = Ts[(4 * ks + lk) * LDP + 16 * mt + lr];
+            acc = mfma_16x16x4(a, w1[ks >> 2][ks & 3], acc);
+        }
+        w2[mt] = acc;
+    }
+    // Zg -= Vp W2   (8 row tiles of the two slots; K = 64 over i)
+#pragma unroll
+    for (int rt = 0; rt < 8; ++rt) {
+        d4 acc = (rt < 4) ? w.z[S0][rt & 3] : w.z[S1][rt & 3];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {          // i4 = 4 ks
+            const int i4 = 4 * ks;
+            if (i4 + 3 < 16 * rt - B + 1 || i4 >= 16 * rt + 16) continue;
+            const double a = -Vp[(16 * rt + lr) * LDP + i4 + lk];
+            acc = mfma_16x16x4(a, w2[ks >> 2][ks & 3], acc);
+        }
+        if (rt < 4) w.z[S0][rt & 3] = acc;
+        else w.z[S1][rt & 3] = acc;
+    }
+}
+
+__device__ __forceinline__ int ngroups_of(const int *goff, int sg) { return goff[sg + 1] - goff[sg]; }
+
+// One time step tau (tau % 4 == P) of a pass with top sweep-block sh.
+template <int P>
+__device__ __forceinline__ void tau_step(Win &w, double *__restrict__ Z, int ldz, int n, int col0, int ncl,
+                                         const double *__restrict__ V2, const double *__restrict__ T2,
+                                         const int *__restrict__ goff, int sh, bool two, int tau, double *Vp,
+                                         double *Ts, double *St)
+{
+    constexpr int SNEW = (P + 3) & 3;
+    if (tau > 0) {
+        store_block<SNEW>(w, Z, ldz, n, col0, ncl, sh + tau - 3, St);
+        load_block<SNEW>(w, Z, ldz, n, col0, ncl, sh + tau + 1, St);
+    }
+    if (tau < ngroups_of(goff, sh))
+        apply_group<(P + 2) & 3, (P + 3) & 3>(w, V2, T2, (size_t)goff[sh] + tau, Vp, Ts);
+    if (two && tau >= 1 && tau - 1 < ngroups_of(goff, sh - 1))
+        apply_group<P & 3, (P + 1) & 3>(w, V2, T2, (size_t)goff[sh - 1] + tau - 1, Vp, Ts);
+}
+
+template <int SL>
+__device__ __forceinline__ void store_final(const Win &w, double *Z, int ldz, int n, int col0, int ncl, int sh,
+                                            int taum, double *St)
+{
+    const int x = sh + taum - 2 + ((SL - taum) & 3);
+    store_block<SL>(w, Z, ldz, n, col0, ncl, x, St);
+}
+
+}  // namespace bt2w
+
+__global__ __launch_bounds__(256) void k_bt2_win(double *__restrict__ Z, int ldz, int n, int ncols,
+                                                 const double *__restrict__ V2, const double *__restrict__ T2,
+                                                 const int *__restrict__ goff, int nsig)
+{
+    using namespace bt2w;
+    extern __shared__ double lds[];
+    double *Vp = lds;                    // 128 x 65
+    double *Ts = Vp + 128 * LDP;         // 64 x 65
+    double *St = Ts + 64 * LDP;          // 64 x 65
+    const int col0 = blockIdx.x * 64;
+    const int ncl = min(64, ncols - col0);
+    // zero part of the parallelogram (the same for every group)
+    for (int e = threadIdx.x; e < 128 * 64; e += 256) {
+        const int r = e >> 6, i = e & 63, d = r - i;
+        if (d < 0 || d >= B) Vp[r * LDP + i] = 0.0;
+    }
+    Win w;
+    for (int sh = nsig - 1; sh >= 0; sh -= 2) {
+        const bool two = sh >= 1;
+        int taum = ngroups_of(goff, sh) - 1;
+        if (two) taum = max(taum, ngroups_of(goff, sh - 1));
+        load_block<0>(w, Z, ldz, n, col0, ncl, sh - 2, St);
+        load_block<1>(w, Z, ldz, n, col0, ncl, sh - 1, St);
+        load_block<2>(w, Z, ldz, n, col0, ncl, sh, St);
+        load_block<3>(w, Z, ldz, n, col0, ncl, sh + 1, St);
+        for (int tau = 0; tau <= taum; tau += 4) {
+            tau_step<0>(w, Z, ldz, n, col0, ncl, V2, T2, goff, sh, two, tau, Vp, Ts, St);
+            if (tau + 1 <= taum) tau_step<1>(w, Z, ldz, n, col0, ncl, V2, T2, goff, sh, two, tau + 1, Vp, Ts, St);
+            if (tau + 2 <= taum) tau_step<2>(w, Z, ldz, n, col0, ncl, V2, T2, goff, sh, two, tau + 2, Vp, Ts, St);
+            if (tau + 3 <= taum) tau_step<3>(w, Z, ldz, n, col0, ncl, V2, T2, goff, sh, two, tau + 3, Vp, Ts, St);
+        }
+        store_final<0>(w, Z, ldz, n, col0, ncl, sh, taum, St);
+        store_final<1>(w, Z, ldz, n, col0, ncl, sh, taum, St);
+        store_final<2>(w, Z, ldz, n, col0, ncl, sh, taum, St);
+        store_final<3>(w, Z, ldz, n, col0, ncl, sh, taum, St);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage-1 back-transformation, fused: Z[r0:n, slab] -= V (T (V^T Z[r0:n, slab]))
+// for one compact-WY block of KK columns (one panel, or two consecutive panels
+// merged: V = [V_j, V_{j+1} shifted down by b rows], T = [[T_j, T12], [0, T_{j+1}]]).
+// One workgroup per 64-column slab: W = V^T Z (K = m rows), W2 = T W, then
+// the slab is updated in row tiles of 128.  W lives in LDS.
+template <typename T, int KK>
+__global__ __launch_bounds__(256) void k_bt1_fused(T *__restrict__ Z, int ldz, int r0, int m, int ncols,
+                                                   const T *__restrict__ V1, int b1, const T *__restrict__ V2,
+                                                   int m2, const double *__restrict__ Tm)
+{
+    constexpr int TN = 64, TMU = 128, LDW = TN + 1;
+    extern __shared__ char smraw[];
+    T *smem = (T *)smraw;
+    constexpr size_t eng = gemm::smem_bytes<T, (KK > TMU ? KK : TMU), TN>() / sizeof(T);
+    T *Wl = smem + eng;                              // KK x 65
+    const int c0 = blockIdx.x * TN;
+    T *Zr = Z + r0;
+    // merged V: column k < b1 from V1 (m rows), k >= b1 from V2 (rows shifted by b1)
+    auto vget = [=](int row, int k) -> T {
+        if (row >= m) return T(0);
+        if (k < b1) return V1[(size_t)k * m + row];
+        if (!V2) return T(0);
+        const int r2 = row - b1;
+        return (r2 >= 0 && r2 < m2) ? V2[(size_t)(k - b1) * m2 + r2] : T(0);
+    };
+    // phase 1: W = V^T Z_slab
+    {
+        auto fa = [=](int l, int row) -> T { return (l < KK) ? vget(row, l) : T(0); };
+        auto fb = [=](int j, int row) -> T {
+            return (row < m && c0 + j < ncols) ? Zr[(size_t)(c0 + j) * ldz + row] : T(0);
+        };
+        gemm::Acc<T, KK, TN> acc;
+        acc.zero();
+        gemm::kloop<T, KK, TN, true, true>(fa, fb, 0, 0, 0, m, smem, acc);
+        gemm::epilogue<T, KK, TN>(acc, smem, [=](int i, int j, T v) { Wl[i * LDW + j] = v; });
+    }
+    __syncthreads();
+    // phase 2: W2 = T W  (T: KK x KK column-major, double)
+    {
+        auto fa = [=](int i, int k) -> T { return (T)Tm[(size_t)k * KK + i]; };
+        auto fb = [=](int j, int k) -> T { return Wl[k * LDW + j]; };
+        gemm::Acc<T, KK, TN> acc;
+        acc.zero();
+        gemm::kloop<T, KK, TN, false, false>(fa, fb, 0, 0, 0, KK, smem, acc);
+        gemm::epilogue<T, KK, TN>(acc, smem, [=](int i, int j, T v) { Wl[i * LDW + j] = v; });
+    }
+    __syncthreads();
+    // phase 3: Z_slab -= V W2, row tiles of 128
+    for (int m0 = 0; m0 < m; m0 += TMU) {
+        auto fa = [=](int row, int k) -> T { return vget(row, k); };
+        auto fb = [=](int j, int k) -> T { return Wl[k * LDW + j]; };
+        gemm::Acc<T, TMU, TN> acc;
+        acc.zero();
+        gemm::kloop<T, TMU, TN, false, false>(fa, fb, m0, 0, 0, KK, smem, acc);
+        gemm::epilogue_rmw<T, TMU, TN>(
+            acc, smem,
+            [=](int i, int j) -> T {
+                const int gi = m0 + i, gj = c0 + j;
+                return (gi < m && gj < ncols) ? Zr[(size_t)gj * ldz + gi] : T(0);
+            },
+            [=](int i, int j, T old, T v) {
+                const int gi = m0 + i, gj = c0 + j;
+                if (gi < m && gj < ncols) Zr[(size_t)gj * ldz + gi] = old - v;
+            });
+    }
+}
+
+// Merged T of two consecutive panels: Tm = [[T1, -T1 G T2], [0, T2]] with
+// G = sum of the partial products V1(b:, :)^T V2 (b x b each).
+__global__ __launch_bounds__(256) void k_merge_t(const double *__restrict__ T1, const double *__restrict__ T2,
+                                                 const double *__restrict__ Gp, int S, int b,
+                                                 double *__restrict__ Tm)
+{
+    __shared__ double G[64 * 65], M1[64 * 65];
+    const int tid = threadIdx.x, bb = b * b, K = 2 * b;
+    {
+        double acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = tid + 256 * q;
+                if (e < bb) acc[q] += Gp[(size_t)p * bb + e];
+            }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + 256 * q;
+            if (e < bb) G[(e % b) * 65 + e / b] = acc[q];        // G[u][v]
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < bb; e += 256) {            // M1 = G T2
+        const int u = e % b, v = e / b;
+        double s = 0.0;
+        for (int w = 0; w <= v; ++w) s += G[u * 65 + w] * T2[(size_t)v * b + w];
+        M1[u * 65 + v] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < K * K; e += 256) {
+        const int i = e % K, j = e / K;
+        double val = 0.0;
+        if (i < b && j < b) val = T1[(size_t)j * b + i];
+        else if (i >= b && j >= b) val = T2[(size_t)(j - b) * b + (i - b)];
+        else if (i < b && j >= b) {
+            double s = 0.0;
+            for (int u = i; u < b; ++u) s += T1[(size_t)u * b + i] * M1[u * 65 + (j - b)];
+            val = -s;
+        }
+        Tm[e] = val;
+    }
+}
+
 // Cpart[s] = A[kb:ke, 0:M]^T B[kb:ke, 0:N]   (A: K x M, B: K x N, column-major)
 template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256) void k_gemm_tn_part(const T *__restrict__ A, int lda, const T *__restrict__ B,
@@ -270,10 +598,19 @@ __global__ __launch_bounds__(256) void k_reduce_left(const double *__restrict__ 
     extern __shared__ double cs[];        // M (+ M*M when S0)
     const size_t pst = (size_t)M * N;
     const int j = blockIdx.x;
-    for (int u = threadIdx.x; u < M; u += 256) {
-        double c = 0.0;
-        for (int p = 0; p < S; ++p) c += Cpart[p * pst + (size_t)j * M + u];
-        cs[u] = c;
+    for (int u0 = 0; u0 < M; u0 += 1024) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int u = u0 + threadIdx.x + 256 * q;
+                if (u < M) acc[q] += Cpart[p * pst + (size_t)j * M + u];
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int u = u0 + threadIdx.x + 256 * q;
+            if (u < M) cs[u] = acc[q];
+        }
     }
     if (!S0) {
         for (int u = threadIdx.x; u < M; u += 256) out[(size_t)j * M + u] = cs[u];
@@ -324,8 +661,19 @@ void launch_bt2(T *Z, int ldz, int n, int ncols, int b, int nb2, const double *V
     if (ngroups <= 0 || ncols <= 0) return;
     hipLaunchKernelGGL(k_bt2_tfac<T>, dim3(ngroups), dim3(256), 0, st, V2, tau2, b, nb2, T2, V2t);
     const T *Vuse = V2t ? (const T *)V2t : (const T *)(const void *)V2;
-    hipLaunchKernelGGL(k_bt2_apply<T>, dim3(cdiv(ncols, 64)), dim3(256), 0, st, Z, ldz, n, ncols, b, nb2, Vuse,
-                       (const T *)T2, goff_dev, nsig);
+    if (sizeof(T) == sizeof(double) && b == 64 && nb2 == 64) {
+        const size_t shm = sizeof(double) * (size_t)(128 + 64 + 64) * bt2w::LDP;
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void *)k_bt2_win, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_bt2_win, dim3(cdiv(ncols, 64)), dim3(256), shm, st, (double *)(void *)Z, ldz, n, ncols,
+                           V2, (const double *)(const void *)T2, goff_dev, nsig);
+    } else {
+        hipLaunchKernelGGL(k_bt2_apply<T>, dim3(cdiv(ncols, 64)), dim3(256), 0, st, Z, ldz, n, ncols, b, nb2, Vuse,
+                           (const T *)T2, goff_dev, nsig);
+    }
 }
 
 int tn_splits(int K, int tiles)
@@ -392,6 +740,43 @@ void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int nc
                        dst, ldd, m);
 }
 
+template <typename T>
+void launch_bt1_fused(T *Z, int ldz, int r0, int m, int ncols, const T *V1, int b1, const T *V2, int m2,
+                      const double *Tm, int KK, hipStream_t st)
+{
+    constexpr int TN = 64;
+    if (KK == 128) {
+        const size_t shm = (gemm::smem_bytes<T, 128, TN>()) + sizeof(T) * 128 * (TN + 1);
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void *)k_bt1_fused<T, 128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)shm);
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_bt1_fused<T, 128>), dim3(cdiv(ncols, TN)), dim3(256), shm, st, Z, ldz, r0, m, ncols, V1,
+                           b1, V2, m2, Tm);
+    } else {
+        const size_t shm = (gemm::smem_bytes<T, 128, TN>()) + sizeof(T) * 64 * (TN + 1);
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void *)k_bt1_fused<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)shm);
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_bt1_fused<T, 64>), dim3(cdiv(ncols, TN)), dim3(256), shm, st, Z, ldz, r0, m, ncols, V1,
+                           b1, V2, m2, Tm);
+    }
+}
+
+void launch_merge_t(const double *T1, const double *T2, const double *Gp, int S, int b, double *Tm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_merge_t, dim3(1), dim3(256), 0, st, T1, T2, Gp, S, b, Tm);
+}
+
+template void launch_bt1_fused<double>(double *, int, int, int, int, const double *, int, const double *, int,
+                                       const double *, int, hipStream_t);
+template void launch_bt1_fused<float>(float *, int, int, int, int, const float *, int, const float *, int,
+                                      const double *, int, hipStream_t);
 template void launch_dscale<double>(const double *, int, int, int, double *, int, hipStream_t);
 template void launch_dscale<float>(const double *, int, int, int, float *, int, hipStream_t);
 template void launch_bt2<double>(double *, int, int, int, int, int, const double *, const double *, double *,

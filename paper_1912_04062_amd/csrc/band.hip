@@ -101,16 +101,25 @@ __global__ __launch_bounds__(256) void k_panel_qr(T *__restrict__ W, int ldw, in
         if (tid < B) {
             double s = 0.0;
             for (int p = 0; p < NP; ++p) s += red[p * B + tid];
-            pbuf[((size_t)par * G + wg) * B + tid] = s;
-            if (wg == 0) pvbuf[par * B + tid] = (l < L) ? P[l * B + tid] : 0.0;
+            st_coh(&pbuf[((size_t)par * G + wg) * B + tid], s);
+            if (wg == 0) st_coh(&pvbuf[par * B + tid], (l < L) ? P[l * B + tid] : 0.0);
         }
         ++nbar;
-        if (!grid_sync(bar, bar_base + nbar * G, err)) return;
+        if (!grid_sync_coh(bar, bar_base + nbar * G, err)) return;
         if (tid < B) {
+            // batches of independent loads; the summation order (w ascending)
+            // is the same in every workgroup
             double s = 0.0;
-            for (int w = 0; w < G; ++w) s += pbuf[((size_t)par * G + w) * B + tid];
+            for (int w0 = 0; w0 < G; w0 += 16) {
+                double t16[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    t16[q] = (w0 + q < G) ? ld_coh(&pbuf[((size_t)par * G + w0 + q) * B + tid]) : 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) s += t16[q];
+            }
             tot[tid] = s;
-            piv[tid] = pvbuf[par * B + tid];
+            piv[tid] = ld_coh(&pvbuf[par * B + tid]);
         }
         __syncthreads();
         // ---- T column l-1: T[0:l-1, l-1] = -tau_{l-1} T[0:l-1, 0:l-1] z
@@ -250,11 +259,24 @@ __global__ __launch_bounds__(256) void k_small(const double *__restrict__ Gp, in
 {
     __shared__ double G[64 * 64], Tm[64 * 64], M1[64 * 64];
     const int tid = threadIdx.x, BB = B * B;
-    for (int e = tid; e < BB; e += 256) {
-        double s = 0.0;
-        for (int c = 0; c < nchunk; ++c) s += Gp[(size_t)c * BB + e];
-        G[e] = s;
-        Tm[e] = Tf[e];
+    {
+        double acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+        for (int c = 0; c < nchunk; ++c)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = tid + 256 * q;
+                if (e < BB) acc[q] += Gp[(size_t)c * BB + e];
+            }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + 256 * q;
+            if (e < BB) {
+                G[e] = acc[q];
+                Tm[e] = Tf[e];
+            }
+        }
     }
     __syncthreads();
     for (int e = tid; e < BB; e += 256) {       // M1 = G T

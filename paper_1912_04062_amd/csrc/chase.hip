@@ -35,30 +35,66 @@ constexpr int CH_LD = 65;
 
 __device__ __forceinline__ int nsteps_of(int n, int b, int s) { return 1 + (n - 2 - s) / b; }
 
+// The below block of step k, A[R_{k+1}, R_k], is exactly the next step's
+// pivot column (its column 0) and left block (columns 1..b-1), and no other
+// sweep writes it between the two steps (sweep s-1 is then at steps >= k+3,
+// which start at row s + (k+3) b).  It therefore stays in LDS (two buffers,
+// alternating), the next reflector is computed from it before waiting on the
+// previous sweep, and only the diagonal block and the new below block are
+// loaded after the wait.
 __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, int ldab, int n, int b,
                                                      int nb2, double *__restrict__ V2,
                                                      double *__restrict__ tau2,
                                                      const int *__restrict__ goff,
                                                      unsigned *progress, unsigned *err)
 {
-    __shared__ double x[64], v[64], y[64], wv[64], dots[64], y2[64];
+    __shared__ double v[64], wv[64], dots[64], y2[64];
     __shared__ double dia[64 * CH_LD];
-    __shared__ double lft[64 * CH_LD];
-    __shared__ double blw[64 * CH_LD];
+    __shared__ double bw[2][64 * CH_LD];
     __shared__ double scal[2];
     __shared__ int abort_flag;
     const int tid = threadIdx.x;
     if (tid == 0) abort_flag = 0;
     __syncthreads();
 
+    // Householder reflector of x (L entries, lane i holds x_i) by wavefront 0;
+    // writes v, scal and the reduced column back to the band.
+    auto reflect = [&](double xi, int L, int c, int lo) {
+        double sq = (tid >= 1 && tid < L) ? xi * xi : 0.0;
+        sq = wave_sum(sq);
+        const double x0 = __shfl(xi, 0, 64);
+        double t = 0.0, beta = x0, scale = 0.0;
+        if (sq != 0.0) {
+            const double nrm = sqrt(x0 * x0 + sq);
+            beta = (x0 >= 0.0) ? -nrm : nrm;
+            t = (beta - x0) / beta;
+            scale = 1.0 / (x0 - beta);
+        }
+        v[tid] = (tid == 0) ? 1.0 : ((tid < L) ? xi * scale : 0.0);
+        if (tid == 0) { scal[0] = t; scal[1] = beta; }
+        if (tid < L) st_coh(&ab[(size_t)c * ldab + (lo + tid - c)], (tid == 0) ? beta : 0.0);
+    };
+
     for (int s = blockIdx.x; s < n - 2; s += gridDim.x) {
         const int nst = nsteps_of(n, b, s);
         const int nprev = (s > 0) ? nsteps_of(n, b, s - 1) : 0;
         const int sig = s / nb2, col = s % nb2;
+        int cur = 0;                              // buffer holding the previous below block
         for (int k = 0; k < nst; ++k) {
+            const int lo = s + 1 + k * b;
+            const int c = (k == 0) ? s : lo - b;
+            const int hi = min(lo + b - 1, n - 1);
+            const int L = hi - lo + 1;
+            const int bhi = min(hi + b, n - 1);
+            const int L2 = bhi - hi;
+            const int nlc = lo - c - 1;           // 0 for k = 0, b - 1 otherwise
+            const double *lb = bw[cur];           // previous below block: rows R_k, cols R_{k-1}
+            double *nb = bw[cur ^ 1];
+            // reflector from the carried pivot column (before the wait)
+            if (k > 0 && tid < 64) reflect((tid < L) ? lb[tid * CH_LD] : 0.0, L, c, lo);
             if (s > 0) {
                 if (tid == 0) {
-                    unsigned need = (unsigned)min(k + 3, nprev);
+                    const unsigned need = (unsigned)min(k + 3, nprev);
                     unsigned spins = 0;
                     while (ld_relaxed(&progress[s - 1]) < need) {
                         __builtin_amdgcn_s_sleep(1);
@@ -68,97 +104,91 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                             break;
                         }
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 __syncthreads();
                 if (abort_flag) return;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-            const int lo = s + 1 + k * b;
-            const int c = (k == 0) ? s : lo - b;
-            const int hi = min(lo + b - 1, n - 1);
-            const int L = hi - lo + 1;
-            const int bhi = min(hi + b, n - 1);
-            const int L2 = bhi - hi;
-            const int nlc = lo - c - 1;  // columns of the left block (0 for k = 0)
-
-            // ---- column c and the reflector
-            if (tid < 64) {
-                double xi = (tid < L) ? ab[(size_t)c * ldab + (lo + tid - c)] : 0.0;
-                double sq = (tid >= 1 && tid < L) ? xi * xi : 0.0;
-                sq = wave_sum(sq);
-                double x0 = __shfl(xi, 0, 64);
-                double t = 0.0, beta = x0, scale = 0.0;
-                if (sq != 0.0) {
-                    double nrm = sqrt(x0 * x0 + sq);
-                    beta = (x0 >= 0.0) ? -nrm : nrm;
-                    t = (beta - x0) / beta;
-                    scale = 1.0 / (x0 - beta);
+            // diagonal and new below block (all loads issued before use)
+            {
+                const int nd = L * L, nbn = L2 * L;
+                double vd[16], vb[16];
+                double x0v = 0.0;
+                if (k == 0 && tid < 64 && tid < L) x0v = ld_coh(&ab[(size_t)c * ldab + (lo + tid - c)]);
+#pragma unroll
+                for (int p = 0; p < 16; ++p) {
+                    const int e = tid + 256 * p;
+                    vd[p] = 0.0;
+                    vb[p] = 0.0;
+                    if (e < nd) {
+                        const int il = e % L, jl = e / L;
+                        if (il > jl) vd[p] = ld_coh(&ab[(size_t)(lo + jl) * ldab + (il - jl)]);
+                    }
+                    if (e < nbn) {
+                        const int il = e % L2, jl = e / L2;
+                        const int i = hi + 1 + il, j = lo + jl;
+                        vb[p] = ld_coh(&ab[(size_t)j * ldab + (i - j)]);
+                    }
                 }
-                v[tid] = (tid == 0) ? 1.0 : ((tid < L) ? xi * scale : 0.0);
-                if (tid == 0) { scal[0] = t; scal[1] = beta; }
-                if (tid < L) ab[(size_t)c * ldab + (lo + tid - c)] = (tid == 0) ? beta : 0.0;
-            }
-            // ---- load the three blocks
-            for (int e = tid; e < L * nlc; e += 256) {          // left: rows R, cols c+1..lo-1
-                int il = e % L, jl = e / L;
-                int j = c + 1 + jl;
-                lft[il * CH_LD + jl] = ab[(size_t)j * ldab + (lo + il - j)];
-            }
-            for (int e = tid; e < L * L; e += 256) {             // diagonal block, full skew
-                int il = e % L, jl = e / L;
-                double a = 0.0;
-                if (il > jl) a = ab[(size_t)(lo + jl) * ldab + (il - jl)];
-                else if (il < jl) a = -ab[(size_t)(lo + il) * ldab + (jl - il)];
-                dia[il * CH_LD + jl] = a;
-            }
-            for (int e = tid; e < L2 * L; e += 256) {            // below: rows hi+1..bhi, cols R
-                int il = e % L2, jl = e / L2;
-                int i = hi + 1 + il, j = lo + jl;
-                blw[il * CH_LD + jl] = ab[(size_t)j * ldab + (i - j)];
+                if (k == 0 && tid < 64) reflect(x0v, L, c, lo);
+#pragma unroll
+                for (int p = 0; p < 16; ++p) {
+                    const int e = tid + 256 * p;
+                    if (e < nd) {
+                        const int il = e % L, jl = e / L;
+                        if (il > jl) {
+                            dia[il * CH_LD + jl] = vd[p];
+                            dia[jl * CH_LD + il] = -vd[p];
+                        } else if (il == jl) {
+                            dia[il * CH_LD + il] = 0.0;
+                        }
+                    }
+                    if (e < nbn) nb[(e % L2) * CH_LD + e / L2] = vb[p];
+                }
             }
             __syncthreads();
             const double t = scal[0];
             // ---- products with v
             if (tid < 64) {
-                if (tid < nlc) {
+                if (tid < nlc) {                  // left block = columns 1.. of the carried block
                     double s2 = 0.0;
-                    for (int il = 0; il < L; ++il) s2 += v[il] * lft[il * CH_LD + tid];
+                    for (int il = 0; il < L; ++il) s2 += v[il] * lb[il * CH_LD + 1 + tid];
                     dots[tid] = t * s2;
                 }
             } else if (tid < 128) {
-                int il = tid - 64;
+                const int il = tid - 64;
                 if (il < L) {
                     double s2 = 0.0;
                     for (int jl = 0; jl < L; ++jl) s2 += dia[il * CH_LD + jl] * v[jl];
-                    y[il] = s2;
                     wv[il] = t * s2;
                 }
             } else if (tid < 192) {
-                int il = tid - 128;
+                const int il = tid - 128;
                 if (il < L2) {
                     double s2 = 0.0;
-                    for (int jl = 0; jl < L; ++jl) s2 += blw[il * CH_LD + jl] * v[jl];
+                    for (int jl = 0; jl < L; ++jl) s2 += nb[il * CH_LD + jl] * v[jl];
                     y2[il] = t * s2;
                 }
             }
             __syncthreads();
-            // ---- updates, written straight back
+            // ---- updates, written back (the new below block also stays in LDS)
             for (int e = tid; e < L * nlc; e += 256) {
-                int il = e % L, jl = e / L;
-                int j = c + 1 + jl;
-                ab[(size_t)j * ldab + (lo + il - j)] = lft[il * CH_LD + jl] - v[il] * dots[jl];
+                const int il = e % L, jl = e / L;
+                const int j = c + 1 + jl;
+                st_coh(&ab[(size_t)j * ldab + (lo + il - j)], lb[il * CH_LD + 1 + jl] - v[il] * dots[jl]);
             }
             for (int e = tid; e < L * L; e += 256) {
-                int il = e % L, jl = e / L;
+                const int il = e % L, jl = e / L;
                 if (il > jl)
-                    ab[(size_t)(lo + jl) * ldab + (il - jl)] =
-                        dia[il * CH_LD + jl] + v[il] * wv[jl] - wv[il] * v[jl];
+                    st_coh(&ab[(size_t)(lo + jl) * ldab + (il - jl)],
+                           dia[il * CH_LD + jl] + v[il] * wv[jl] - wv[il] * v[jl]);
             }
             for (int e = tid; e < L2 * L; e += 256) {
-                int il = e % L2, jl = e / L2;
-                int i = hi + 1 + il, j = lo + jl;
-                ab[(size_t)j * ldab + (i - j)] = blw[il * CH_LD + jl] - y2[il] * v[jl];
+                const int il = e % L2, jl = e / L2;
+                const int i = hi + 1 + il, j = lo + jl;
+                const double val = nb[il * CH_LD + jl] - y2[il] * v[jl];
+                nb[il * CH_LD + jl] = val;
+                st_coh(&ab[(size_t)j * ldab + (i - j)], val);
             }
             // ---- reflector for the back-transformation
             {
@@ -166,9 +196,9 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 if (tid < b) V2[(g * nb2 + col) * b + tid] = (tid < L) ? v[tid] : 0.0;
                 if (tid == 0) tau2[g * nb2 + col] = t;
             }
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) st_release(&progress[s], (unsigned)(k + 1));
+            wg_publish();
+            if (tid == 0) st_relaxed(&progress[s], (unsigned)(k + 1));
+            cur ^= 1;
         }
     }
 }

@@ -50,6 +50,56 @@ __device__ __forceinline__ void add_release(unsigned *p, unsigned v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Coherent (agent-scope, relaxed) element accesses for data exchanged between
+// workgroups inside one kernel: they bypass the per-XCD caches' stale lines
+// without the whole-cache write-back/invalidate that agent-scope fences cost.
+__device__ __forceinline__ double ld_coh(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(unsigned *p, unsigned v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish: wait until this thread's earlier (coherent) stores are performed,
+// then the workgroup barrier; after it one thread may set a flag.
+__device__ __forceinline__ void wg_publish()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+}
+
+// Grid barrier for data exchanged with ld_coh/st_coh: only workgroup-scope
+// fences (no whole-cache maintenance); the counter uses relaxed agent-scope
+// atomics.  Returns false when the wait gave up.
+__device__ __forceinline__ bool grid_sync_coh(unsigned *ctr, unsigned target, unsigned *err)
+{
+    __shared__ int gs_ok;
+    wg_publish();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        int ok = 1;
+        while (ld_relaxed(ctr) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > SKEW_SPIN_LIMIT) {
+                atomicOr(err, 1u);
+                ok = 0;
+                break;
+            }
+        }
+        gs_ok = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return gs_ok != 0;
+}
+
 // Grid-wide barrier for cooperatively launched kernels: a monotonic counter
 // that every workgroup increments once per barrier; `target` is the count at
 // which this barrier opens.  Returns false when the wait gave up.

@@ -58,6 +58,11 @@ void launch_copy_cols(const T *src, int lds, T *dst, int ldd, int m, int ncol, h
 template <typename T>
 void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int ncol, hipStream_t st);
 
+template <typename T>
+void launch_bt1_fused(T *Z, int ldz, int r0, int m, int ncols, const T *V1, int b1, const T *V2, int m2,
+                      const double *Tm, int KK, hipStream_t st);
+void launch_merge_t(const double *T1, const double *T2, const double *Gp, int S, int b, double *Tm, hipStream_t st);
+
 // refine.hip
 template <typename T>
 void launch_build_x(const T *Z, int ldz, int n, int nev, int odd, double *X, hipStream_t st);

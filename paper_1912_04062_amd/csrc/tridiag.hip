@@ -162,18 +162,22 @@ __global__ __launch_bounds__(256) void k_invit(const double *__restrict__ alpha,
     }
     if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
     U0[(size_t)(n - 1) * st + k] = a;
+#pragma unroll 8
     for (int i = 0; i + 1 < n; ++i) {
         double u = U0[i * st + k];
         if (fabs(u) < tiny) U0[i * st + k] = (u < 0.0) ? -tiny : tiny;
     }
     // start vector
+#pragma unroll 8
     for (int i = 0; i < n; ++i) Y[i * st + k] = hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i);
     for (int it = 0; it < iters; ++it) {
         double s = 0.0;
+#pragma unroll 8
         for (int i = 0; i < n; ++i) { double yi = Y[i * st + k]; s += yi * yi; }
         const double inv = 1.0 / sqrt(s);
         // forward: P, L
         double yprev = Y[k] * inv;
+#pragma unroll 8
         for (int i = 0; i + 1 < n; ++i) {
             double ynext = Y[(i + 1) * st + k] * inv;
             double yi = yprev;
@@ -185,6 +189,7 @@ __global__ __launch_bounds__(256) void k_invit(const double *__restrict__ alpha,
         Y[(size_t)(n - 1) * st + k] = yprev;
         // backward: U
         double x1 = 0.0, x2 = 0.0;
+#pragma unroll 8
         for (int i = n - 1; i >= 0; --i) {
             double r = Y[i * st + k];
             if (i + 1 < n) r -= U1[i * st + k] * x1;
@@ -197,7 +202,9 @@ __global__ __launch_bounds__(256) void k_invit(const double *__restrict__ alpha,
     }
     // normalise; for lambda > 0 the even and odd halves each to 1/sqrt(2)
     double se = 0.0, so = 0.0;
+#pragma unroll 8
     for (int i = 0; i < n; i += 2) { double yi = Y[i * st + k]; se += yi * yi; }
+#pragma unroll 8
     for (int i = 1; i < n; i += 2) { double yi = Y[i * st + k]; so += yi * yi; }
     double fe, fo;
     if (lam > 0.0 && se > 0.0 && so > 0.0) {
@@ -206,6 +213,7 @@ __global__ __launch_bounds__(256) void k_invit(const double *__restrict__ alpha,
     } else {
         fe = fo = 1.0 / sqrt(se + so);
     }
+#pragma unroll 8
     for (int i = 0; i < n; ++i) Y[i * st + k] *= (i & 1) ? fo : fe;
 }
 
@@ -259,10 +267,22 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp,
 {
     __shared__ double G[64 * 65], R[64 * 65];
     const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += 256) {
-        double s = 0.0;
-        for (int p = 0; p < nparts; ++p) s += Gp[(size_t)p * NB * NB + e];
-        G[(e % NB) * 65 + e / NB] = s;      // G[i][j]
+    {
+        // 16 independent sums per thread: the loads of one partial are issued together
+        double acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+        for (int p = 0; p < nparts; ++p)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = tid + 256 * q;
+                if (e < NB * NB) acc[q] += Gp[(size_t)p * NB * NB + e];
+            }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + 256 * q;
+            if (e < NB * NB) G[(e % NB) * 65 + e / NB] = acc[q];   // G[i][j]
+        }
     }
     for (int e = tid; e < 64 * 65; e += 256) R[e] = 0.0;
     __syncthreads();

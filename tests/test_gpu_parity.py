@@ -196,3 +196,19 @@ def test_batched_matches_single(h):
         assert np.array_equal(zr.cpu().numpy(), z1r.cpu().numpy())
         lref, _ = oracle.skew_evd(A)
         assert np.max(np.abs(lam.cpu().numpy() - lref)) <= TOL_EIG * lref.max()
+
+
+@pytest.mark.parametrize("n,b", [(130, 64), (300, 64), (701, 64), (1000, 64), (700, 16), (1000, 32)])
+def test_solve_band_widths(h, n, b):
+    """Every band width path of the back-transformations, with ragged tails."""
+    _log(f"solve n={n} band={b}")
+    A = wl.random_skew(n, 1300 + n + b)
+    lam, Z = solve_np(h, A, band=b)
+    lref, Zref = oracle.skew_evd(A)
+    nA = lref.max()
+    assert np.max(np.abs(lam - lref)) <= TOL_EIG * nA
+    res, orth, _ = metrics(A, lam, Z, nA)
+    _log(f"  res={res:.2e} orth={orth:.2e}")
+    assert res <= TOL_RES and orth <= TOL_ORTH
+    ok, worst = phase_match(Z, Zref, lref, 1e-4 * nA, 1e-10)
+    assert ok, worst
