@@ -17,11 +17,18 @@
 //   from the right  to A[hi+1..hi+b, R_k] (this creates the next bulge).
 // The reflector of step k+1 comes from column lo of that bulge.
 //
-// Pipelining: sweep s+1 may run step k once sweep s has completed step k+2
-// (or all its steps); this orders every pair of steps that touch a common
-// entry.  Sweeps are dealt round-robin to the workgroups of a cooperative
-// launch; per-sweep progress counters carry the dependency (agent-scope
-// release/acquire), and every wait is bounded.
+// Pipelining: sweep s+1 may run step k once sweep s has completed step k+1
+// and has published the first entry (beta) of the pivot column of its step
+// k+2.  Step k+2 of sweep s touches exactly one entry that step k of sweep
+// s+1 also touches: that beta, in the last row of the block below the
+// diagonal block; it is known as soon as the reflector of step k+2 is formed
+// (before sweep s waits for sweep s-1), so it is published first.  Every
+// other pair of steps that touches a common entry is ordered by the
+// completion of step k+1.  The per-sweep counter progress[s] holds
+// 2*(steps completed) + 1 once the next step's beta is in memory, and
+// 2*nsteps + 1 when the sweep is done; a waiting step needs
+// min(2k + 5, 2 nsteps(s) + 1).  Sweeps are dealt round-robin to the
+// workgroups of a cooperative launch and every wait is bounded.
 //
 // Each reflector is written, for the back-transformation, into the group of
 // nb2 consecutive sweeps at the same step k: V2[g][col][0..b) with
@@ -37,11 +44,15 @@ __device__ __forceinline__ int nsteps_of(int n, int b, int s) { return 1 + (n - 
 
 // The below block of step k, A[R_{k+1}, R_k], is exactly the next step's
 // pivot column (its column 0) and left block (columns 1..b-1), and no other
-// sweep writes it between the two steps (sweep s-1 is then at steps >= k+3,
-// which start at row s + (k+3) b).  It therefore stays in LDS (two buffers,
-// alternating), the next reflector is computed from it before waiting on the
-// previous sweep, and only the diagonal block and the new below block are
-// loaded after the wait.
+// sweep writes it between the two steps except for the beta entry, which is
+// in place before the step's wait ends.  It therefore stays in LDS (two
+// buffers, alternating) and the next reflector is computed from it before
+// waiting on the previous sweep; only the diagonal block and the new below
+// block are loaded after the wait.
+//
+// Thread (tx, ty) = (tid % 64, tid / 64) owns row tx and columns ty + 4q
+// (q = 0..15) of the 64 x 64 blocks, so every global access of a wavefront is
+// one contiguous run of a band column and no index needs a division.
 __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, int ldab, int n, int b,
                                                      int nb2, double *__restrict__ V2,
                                                      double *__restrict__ tau2,
@@ -49,17 +60,19 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                                                      unsigned *progress, unsigned *err)
 {
     __shared__ double v[64], wv[64], dots[64], y2[64];
+    __shared__ double pw[4][64], py[4][64], pd[4][64];
     __shared__ double dia[64 * CH_LD];
     __shared__ double bw[2][64 * CH_LD];
     __shared__ double scal[2];
     __shared__ int abort_flag;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     if (tid == 0) abort_flag = 0;
     __syncthreads();
 
     // Householder reflector of x (L entries, lane i holds x_i) by wavefront 0;
-    // writes v, scal and the reduced column back to the band.
-    auto reflect = [&](double xi, int L, int c, int lo) {
+    // writes v, scal and the reduced column (beta, 0, ..., 0) to the band,
+    // then publishes the beta (counter value `flag`).
+    auto reflect = [&](double xi, int L, int c, int lo, int s, unsigned flag) {
         double sq = (tid >= 1 && tid < L) ? xi * xi : 0.0;
         sq = wave_sum(sq);
         const double x0 = __shfl(xi, 0, 64);
@@ -73,6 +86,8 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
         v[tid] = (tid == 0) ? 1.0 : ((tid < L) ? xi * scale : 0.0);
         if (tid == 0) { scal[0] = t; scal[1] = beta; }
         if (tid < L) st_coh(&ab[(size_t)c * ldab + (lo + tid - c)], (tid == 0) ? beta : 0.0);
+        wait_vmem();
+        if (tid == 0) st_relaxed(&progress[s], flag);
     };
 
     for (int s = blockIdx.x; s < n - 2; s += gridDim.x) {
@@ -91,10 +106,10 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
             const double *lb = bw[cur];           // previous below block: rows R_k, cols R_{k-1}
             double *nb = bw[cur ^ 1];
             // reflector from the carried pivot column (before the wait)
-            if (k > 0 && tid < 64) reflect((tid < L) ? lb[tid * CH_LD] : 0.0, L, c, lo);
+            if (k > 0 && tid < 64) reflect((tid < L) ? lb[tid * CH_LD] : 0.0, L, c, lo, s, 2u * k + 1u);
             if (s > 0) {
                 if (tid == 0) {
-                    const unsigned need = (unsigned)min(k + 3, nprev);
+                    const unsigned need = (unsigned)min(2 * k + 5, 2 * nprev + 1);
                     unsigned spins = 0;
                     while (ld_relaxed(&progress[s - 1]) < need) {
                         __builtin_amdgcn_s_sleep(1);
@@ -109,86 +124,73 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 if (abort_flag) return;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-            // diagonal and new below block (all loads issued before use)
+            // diagonal block (strict lower part) and new below block, all
+            // loads issued before use
+            double vd[16], vb[16];
             {
-                const int nd = L * L, nbn = L2 * L;
-                double vd[16], vb[16];
                 double x0v = 0.0;
                 if (k == 0 && tid < 64 && tid < L) x0v = ld_coh(&ab[(size_t)c * ldab + (lo + tid - c)]);
+                const bool rowd = tx < L, rowb = tx < L2;
 #pragma unroll
-                for (int p = 0; p < 16; ++p) {
-                    const int e = tid + 256 * p;
-                    vd[p] = 0.0;
-                    vb[p] = 0.0;
-                    if (e < nd) {
-                        const int il = e % L, jl = e / L;
-                        if (il > jl) vd[p] = ld_coh(&ab[(size_t)(lo + jl) * ldab + (il - jl)]);
-                    }
-                    if (e < nbn) {
-                        const int il = e % L2, jl = e / L2;
-                        const int i = hi + 1 + il, j = lo + jl;
-                        vb[p] = ld_coh(&ab[(size_t)j * ldab + (i - j)]);
-                    }
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = ty + 4 * q;
+                    vd[q] = 0.0;
+                    vb[q] = 0.0;
+                    if (rowd && tx > jl) vd[q] = ld_coh(&ab[(size_t)(lo + jl) * ldab + (tx - jl)]);
+                    if (rowb && jl < L) vb[q] = ld_coh(&ab[(size_t)(lo + jl) * ldab + (hi + 1 + tx - lo - jl)]);
                 }
-                if (k == 0 && tid < 64) reflect(x0v, L, c, lo);
+                if (k == 0 && tid < 64) reflect(x0v, L, c, lo, s, 1u);
+                // full skew block in LDS (zeros outside L x L)
 #pragma unroll
-                for (int p = 0; p < 16; ++p) {
-                    const int e = tid + 256 * p;
-                    if (e < nd) {
-                        const int il = e % L, jl = e / L;
-                        if (il > jl) {
-                            dia[il * CH_LD + jl] = vd[p];
-                            dia[jl * CH_LD + il] = -vd[p];
-                        } else if (il == jl) {
-                            dia[il * CH_LD + il] = 0.0;
-                        }
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = ty + 4 * q;
+                    if (tx > jl) {
+                        dia[tx * CH_LD + jl] = vd[q];
+                        dia[jl * CH_LD + tx] = -vd[q];
+                    } else if (tx == jl) {
+                        dia[tx * CH_LD + tx] = 0.0;
                     }
-                    if (e < nbn) nb[(e % L2) * CH_LD + e / L2] = vb[p];
                 }
             }
             __syncthreads();
             const double t = scal[0];
-            // ---- products with v
-            if (tid < 64) {
-                if (tid < nlc) {                  // left block = columns 1.. of the carried block
-                    double s2 = 0.0;
-                    for (int il = 0; il < L; ++il) s2 += v[il] * lb[il * CH_LD + 1 + tid];
-                    dots[tid] = t * s2;
+            // ---- products with v: w = t A v (diagonal block), y2 = t B v
+            // (below block), dots = t v^T C (left block); four partial sums
+            {
+                double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = ty + 4 * q;
+                    const double vj = v[jl];
+                    a1 += dia[tx * CH_LD + jl] * vj;
+                    a2 += vb[q] * vj;
+                    a3 += vj * lb[jl * CH_LD + 1 + tx];
                 }
-            } else if (tid < 128) {
-                const int il = tid - 64;
-                if (il < L) {
-                    double s2 = 0.0;
-                    for (int jl = 0; jl < L; ++jl) s2 += dia[il * CH_LD + jl] * v[jl];
-                    wv[il] = t * s2;
-                }
-            } else if (tid < 192) {
-                const int il = tid - 128;
-                if (il < L2) {
-                    double s2 = 0.0;
-                    for (int jl = 0; jl < L; ++jl) s2 += nb[il * CH_LD + jl] * v[jl];
-                    y2[il] = t * s2;
-                }
+                pw[ty][tx] = a1;
+                py[ty][tx] = a2;
+                pd[ty][tx] = a3;
             }
             __syncthreads();
+            if (ty == 0) wv[tx] = t * (pw[0][tx] + pw[1][tx] + pw[2][tx] + pw[3][tx]);
+            else if (ty == 1) y2[tx] = t * (py[0][tx] + py[1][tx] + py[2][tx] + py[3][tx]);
+            else if (ty == 2) dots[tx] = t * (pd[0][tx] + pd[1][tx] + pd[2][tx] + pd[3][tx]);
+            __syncthreads();
             // ---- updates, written back (the new below block also stays in LDS)
-            for (int e = tid; e < L * nlc; e += 256) {
-                const int il = e % L, jl = e / L;
-                const int j = c + 1 + jl;
-                st_coh(&ab[(size_t)j * ldab + (lo + il - j)], lb[il * CH_LD + 1 + jl] - v[il] * dots[jl]);
-            }
-            for (int e = tid; e < L * L; e += 256) {
-                const int il = e % L, jl = e / L;
-                if (il > jl)
-                    st_coh(&ab[(size_t)(lo + jl) * ldab + (il - jl)],
-                           dia[il * CH_LD + jl] + v[il] * wv[jl] - wv[il] * v[jl]);
-            }
-            for (int e = tid; e < L2 * L; e += 256) {
-                const int il = e % L2, jl = e / L2;
-                const int i = hi + 1 + il, j = lo + jl;
-                const double val = nb[il * CH_LD + jl] - y2[il] * v[jl];
-                nb[il * CH_LD + jl] = val;
-                st_coh(&ab[(size_t)j * ldab + (i - j)], val);
+            {
+                const double vi = v[tx], wi = wv[tx], yi = y2[tx];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = ty + 4 * q;
+                    if (tx < L && jl < nlc) {
+                        const int j = c + 1 + jl;
+                        st_coh(&ab[(size_t)j * ldab + (lo + tx - j)], lb[tx * CH_LD + 1 + jl] - vi * dots[jl]);
+                    }
+                    if (tx < L && tx > jl)
+                        st_coh(&ab[(size_t)(lo + jl) * ldab + (tx - jl)], vd[q] + vi * wv[jl] - wi * v[jl]);
+                    const double val = vb[q] - yi * v[jl];
+                    nb[tx * CH_LD + jl] = val;
+                    if (tx < L2 && jl < L) st_coh(&ab[(size_t)(lo + jl) * ldab + (hi + 1 + tx - lo - jl)], val);
+                }
             }
             // ---- reflector for the back-transformation
             {
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 if (tid == 0) tau2[g * nb2 + col] = t;
             }
             wg_publish();
-            if (tid == 0) st_relaxed(&progress[s], (unsigned)(k + 1));
+            if (tid == 0) st_relaxed(&progress[s], (k + 1 == nst) ? 2u * nst + 1u : 2u * k + 2u);
             cur ^= 1;
         }
     }
@@ -228,8 +230,8 @@ int chase_ngroups(int n, int b, int nb2, int *goff_host)
 }
 
 // Workgroups of the cooperative bulge-chase launch: enough for the sweeps
-// that can be in flight at once (a sweep of n/b steps starts every third
-// step of its predecessor), never more than the device holds.
+// that can be in flight at once (a sweep of n/b steps starts about every
+// second step of its predecessor), never more than the device holds.
 int chase_workgroups(int n, int b)
 {
     int dev = 0, ncu = 256;
@@ -239,7 +241,7 @@ int chase_workgroups(int n, int b)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_bulge_chase, 256, 0);
     if (occ < 1) occ = 1;
     int G = ncu * occ;
-    const int inflight = (n / (b > 0 ? b : 1)) / 3 + 16;
+    const int inflight = (n / (b > 0 ? b : 1)) / 2 + 16;
     if (G > inflight) G = inflight;
     if (G > n - 2) G = n - 2;
     if (G < 1) G = 1;

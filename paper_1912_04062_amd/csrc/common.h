@@ -66,10 +66,18 @@ __device__ __forceinline__ void st_relaxed(unsigned *p, unsigned v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Publish: wait until this thread's earlier (coherent) stores are performed,
-// then the workgroup barrier; after it one thread may set a flag.
+// Wait for this wave's outstanding vector memory operations (s_waitcnt
+// vmcnt(0); expcnt and lgkmcnt left unconstrained).  On gfx950 a
+// workgroup-scope release fence does not wait for global stores, so code that
+// publishes data to other workgroups must wait explicitly.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Publish: wait until this wave's earlier (coherent) stores are performed,
+// then the workgroup barrier; after it one thread may set a flag, and a
+// workgroup that observes the flag reads the data with ld_coh.
 __device__ __forceinline__ void wg_publish()
 {
+    wait_vmem();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
 }
