@@ -128,7 +128,7 @@ Layout plan_layout(const Plan &p)
     L.Qd = take(sizeof(double) * n * nev);
     L.Z = take(es * n * 2 * nev);
     L.Wp = take(sizeof(double) * tn_parts_max() * b * 2 * nev);
-    L.Wt2 = take(sizeof(double) * b * 2 * nev);
+    L.Wt2 = take(sizeof(double) * 2 * b * 2 * nev);
     const size_t wmax = std::max((size_t)p.orth_window, (size_t)ORTH_NB);
     L.Pp = take(sizeof(double) * tn_parts_max() * wmax * ORTH_NB);
     L.P = take(sizeof(double) * wmax * ORTH_NB);
@@ -427,21 +427,17 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L)
             skew::launch_merge_t(ptr<double>(h, L.Tall) + (size_t)j0 * b * b,
                                  ptr<double>(h, L.Tall) + (size_t)(j0 + 1) * b * b, ptr<double>(h, L.Wp), S, b,
                                  ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, st);
-            skew::launch_bt1_fused<T>(Z, n, (j0 + 1) * b, m0, 2 * nev, V0, b, V1, m1,
-                                      ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, 2 * b, st);
+            skew::launch_bt1_block<T>(Z, n, (j0 + 1) * b, m0, 2 * nev, V0, b, V1, m1,
+                                      ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, 2 * b, ptr<double>(h, L.Wp),
+                                      ptr<T>(h, L.Wt2), st);
             HCHK(hipGetLastError());
         }
         if (P % 2 == 1) {                    // panel 0 alone
             const int m0 = n - b;
             const T *V0 = ptr<T>(h, L.Vall) + L.Voff[0];
             const double *Tf = ptr<double>(h, L.Tall);
-            if (b == 64) {
-                skew::launch_bt1_fused<T>(Z, n, b, m0, 2 * nev, V0, b, nullptr, 0, Tf, b, st);
-            } else {
-                int S = skew::launch_gemm_tn_part<T>(V0, m0, Z + b, n, b, 2 * nev, m0, ptr<double>(h, L.Wp), st);
-                skew::launch_reduce_left(Tf, ptr<double>(h, L.Wp), S, b, 2 * nev, ptr<double>(h, L.Wt2), st);
-                skew::launch_gemm_nn<T>(V0, m0, ptr<double>(h, L.Wt2), 1, m0, 2 * nev, b, Z + b, n, -1.0, 1, st);
-            }
+            skew::launch_bt1_block<T>(Z, n, b, m0, 2 * nev, V0, b, nullptr, 0, Tf, b, ptr<double>(h, L.Wp),
+                                      ptr<T>(h, L.Wt2), st);
             HCHK(hipGetLastError());
         }
         HCHK(kt_end(h, SKEW_EVD_K_BT1));

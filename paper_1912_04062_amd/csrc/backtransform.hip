@@ -423,71 +423,100 @@ __global__ __launch_bounds__(256) void k_bt2_win(double *__restrict__ Z, int ldz
 }
 
 // ---------------------------------------------------------------------------
-// Stage-1 back-transformation, fused: Z[r0:n, slab] -= V (T (V^T Z[r0:n, slab]))
-// for one compact-WY block of KK columns (one panel, or two consecutive panels
-// merged: V = [V_j, V_{j+1} shifted down by b rows], T = [[T_j, T12], [0, T_{j+1}]]).
-// One workgroup per 64-column slab: W = V^T Z (K = m rows), W2 = T W, then
-// the slab is updated in row tiles of 128.  W lives in LDS.
-template <typename T, int KK>
-__global__ __launch_bounds__(256) void k_bt1_fused(T *__restrict__ Z, int ldz, int r0, int m, int ncols,
-                                                   const T *__restrict__ V1, int b1, const T *__restrict__ V2,
-                                                   int m2, const double *__restrict__ Tm)
-{
-    constexpr int TN = 64, TMU = 128, LDW = TN + 1;
-    extern __shared__ char smraw[];
-    T *smem = (T *)smraw;
-    constexpr size_t eng = gemm::smem_bytes<T, (KK > TMU ? KK : TMU), TN>() / sizeof(T);
-    T *Wl = smem + eng;                              // KK x 65
-    const int c0 = blockIdx.x * TN;
-    T *Zr = Z + r0;
-    // merged V: column k < b1 from V1 (m rows), k >= b1 from V2 (rows shifted by b1)
-    auto vget = [=](int row, int k) -> T {
+// Stage-1 back-transformation of one compact-WY block of KK reflectors (one
+// panel, or two consecutive panels merged: V = [V_j, V_{j+1} shifted down by
+// b rows], T = [[T_j, T12], [0, T_{j+1}]]):  Z[r0:, :] -= V (T (V^T Z[r0:, :])).
+// Three launches with many workgroups each (two per CU: the register budget
+// is capped so that two waves share every SIMD):
+//   k_bt1_w   Wp[s] = V^T Z over the s-th chunk of rows (split K)
+//   k_bt1_t   W2 = T * sum_s Wp[s]
+//   k_bt1_z   Z -= V W2 on 128 x 64 tiles.
+
+// Element (row, k) of the (merged) V of a block: column k < b1 comes from V1
+// (m rows), k >= b1 from V2 (m2 rows, starting b1 rows lower); 0 elsewhere.
+template <typename T>
+struct MergedV {
+    const T *V1;
+    const T *V2;
+    int b1, m, m2;
+    __device__ __forceinline__ T operator()(int row, int k) const
+    {
         if (row >= m) return T(0);
         if (k < b1) return V1[(size_t)k * m + row];
         if (!V2) return T(0);
         const int r2 = row - b1;
         return (r2 >= 0 && r2 < m2) ? V2[(size_t)(k - b1) * m2 + r2] : T(0);
+    }
+};
+
+template <typename T, int KK>
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_bt1_w(
+    const T *__restrict__ Z, int ldz, int ncols, MergedV<T> V, int kchunk, double *__restrict__ Wp)
+{
+    constexpr int TN = 128;
+    extern __shared__ char smraw[];
+    T *smem = (T *)smraw;
+    const int n0 = blockIdx.x * TN, s = blockIdx.y;
+    const int kb = s * kchunk, ke = min(V.m, kb + kchunk);
+    auto fa = [=](int l, int row) -> T { return (l < KK && row < ke) ? V(row, l) : T(0); };
+    // fetch functors take absolute indices (the engine adds the tile origin)
+    auto fb = [=](int j, int row) -> T { return (row < ke && j < ncols) ? Z[(size_t)j * ldz + row] : T(0); };
+    gemm::Acc<T, KK, TN> acc;
+    acc.zero();
+    gemm::kloop<T, KK, TN, true, true>(fa, fb, 0, n0, kb, ke, smem, acc);
+    double *W = Wp + (size_t)s * KK * ncols;
+    gemm::epilogue<T, KK, TN>(acc, smem, [=](int i, int j, T v) {
+        if (n0 + j < ncols) W[(size_t)(n0 + j) * KK + i] = (double)v;
+    });
+}
+
+template <typename T, int KK>
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_bt1_t(
+    const double *__restrict__ Tm, const double *__restrict__ Wp, int S, int ncols, T *__restrict__ W2)
+{
+    constexpr int TN = 64;
+    extern __shared__ char smraw[];
+    T *smem = (T *)smraw;
+    const int n0 = blockIdx.x * TN;
+    const size_t pst = (size_t)KK * ncols;
+    auto fa = [=](int i, int k) -> T { return (T)Tm[(size_t)k * KK + i]; };
+    auto fb = [=](int j, int k) -> T {
+        if (j >= ncols) return T(0);
+        double sum = 0.0;
+        for (int p = 0; p < S; ++p) sum += Wp[p * pst + (size_t)j * KK + k];
+        return (T)sum;
     };
-    // phase 1: W = V^T Z_slab
-    {
-        auto fa = [=](int l, int row) -> T { return (l < KK) ? vget(row, l) : T(0); };
-        auto fb = [=](int j, int row) -> T {
-            return (row < m && c0 + j < ncols) ? Zr[(size_t)(c0 + j) * ldz + row] : T(0);
-        };
-        gemm::Acc<T, KK, TN> acc;
-        acc.zero();
-        gemm::kloop<T, KK, TN, true, true>(fa, fb, 0, 0, 0, m, smem, acc);
-        gemm::epilogue<T, KK, TN>(acc, smem, [=](int i, int j, T v) { Wl[i * LDW + j] = v; });
-    }
-    __syncthreads();
-    // phase 2: W2 = T W  (T: KK x KK column-major, double)
-    {
-        auto fa = [=](int i, int k) -> T { return (T)Tm[(size_t)k * KK + i]; };
-        auto fb = [=](int j, int k) -> T { return Wl[k * LDW + j]; };
-        gemm::Acc<T, KK, TN> acc;
-        acc.zero();
-        gemm::kloop<T, KK, TN, false, false>(fa, fb, 0, 0, 0, KK, smem, acc);
-        gemm::epilogue<T, KK, TN>(acc, smem, [=](int i, int j, T v) { Wl[i * LDW + j] = v; });
-    }
-    __syncthreads();
-    // phase 3: Z_slab -= V W2, row tiles of 128
-    for (int m0 = 0; m0 < m; m0 += TMU) {
-        auto fa = [=](int row, int k) -> T { return vget(row, k); };
-        auto fb = [=](int j, int k) -> T { return Wl[k * LDW + j]; };
-        gemm::Acc<T, TMU, TN> acc;
-        acc.zero();
-        gemm::kloop<T, TMU, TN, false, false>(fa, fb, m0, 0, 0, KK, smem, acc);
-        gemm::epilogue_rmw<T, TMU, TN>(
-            acc, smem,
-            [=](int i, int j) -> T {
-                const int gi = m0 + i, gj = c0 + j;
-                return (gi < m && gj < ncols) ? Zr[(size_t)gj * ldz + gi] : T(0);
-            },
-            [=](int i, int j, T old, T v) {
-                const int gi = m0 + i, gj = c0 + j;
-                if (gi < m && gj < ncols) Zr[(size_t)gj * ldz + gi] = old - v;
-            });
-    }
+    gemm::Acc<T, KK, TN> acc;
+    acc.zero();
+    gemm::kloop<T, KK, TN, false, true>(fa, fb, 0, n0, 0, KK, smem, acc);
+    gemm::epilogue<T, KK, TN>(acc, smem, [=](int i, int j, T v) {
+        if (n0 + j < ncols) W2[(size_t)(n0 + j) * KK + i] = v;
+    });
+}
+
+template <typename T, int KK>
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_bt1_z(
+    T *__restrict__ Z, int ldz, int ncols, MergedV<T> V, const T *__restrict__ W2)
+{
+    constexpr int TM = 128, TN = 64;
+    extern __shared__ char smraw[];
+    T *smem = (T *)smraw;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    auto fa = [=](int row, int k) -> T { return V(row, k); };
+    auto fb = [=](int j, int k) -> T { return (j < ncols) ? W2[(size_t)j * KK + k] : T(0); };
+    gemm::Acc<T, TM, TN> acc;
+    acc.zero();
+    gemm::kloop<T, TM, TN, false, true>(fa, fb, m0, n0, 0, KK, smem, acc);
+    gemm::epilogue_rmw<T, TM, TN>(
+        acc, smem,
+        [=](int i, int j) -> T {
+            const int gi = m0 + i, gj = n0 + j;
+            return (gi < V.m && gj < ncols) ? Z[(size_t)gj * ldz + gi] : T(0);
+        },
+        [=](int i, int j, T old, T v) {
+            const int gi = m0 + i, gj = n0 + j;
+            if (gi < V.m && gj < ncols) Z[(size_t)gj * ldz + gi] = old - v;
+        });
 }
 
 // Merged T of two consecutive panels: Tm = [[T1, -T1 G T2], [0, T2]] with
@@ -538,7 +567,7 @@ __global__ __launch_bounds__(256) void k_merge_t(const double *__restrict__ T1, 
 
 // Cpart[s] = A[kb:ke, 0:M]^T B[kb:ke, 0:N]   (A: K x M, B: K x N, column-major)
 template <typename T, int TM, int TN>
-__global__ __launch_bounds__(256) void k_gemm_tn_part(const T *__restrict__ A, int lda, const T *__restrict__ B,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_gemm_tn_part(const T *__restrict__ A, int lda, const T *__restrict__ B,
                                                       int ldb, int M, int N, int K, int kchunk,
                                                       double *__restrict__ Cpart)
 {
@@ -560,7 +589,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn_part(const T *__restrict__ A, i
 // C = beta*C + alpha * A (M x K, column-major) * Bsum, Bsum = sum_s Bpart[s]
 // (K x N, column-major ld K, S parts, double).
 template <typename T, int TM, int TN>
-__global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int lda, const double *__restrict__ Bpart,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_gemm_nn(const T *__restrict__ A, int lda, const double *__restrict__ Bpart,
                                                  int S, int M, int N, int K, T *__restrict__ C, int ldc,
                                                  double alpha, int beta)
 {
@@ -740,32 +769,43 @@ void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int nc
                        dst, ldd, m);
 }
 
-template <typename T>
-void launch_bt1_fused(T *Z, int ldz, int r0, int m, int ncols, const T *V1, int b1, const T *V2, int m2,
-                      const double *Tm, int KK, hipStream_t st)
+// Split of the row range of k_bt1_w: about two workgroups per CU, chunks of
+// at least 512 rows.
+int bt1_splits(int m, int ncols)
 {
-    constexpr int TN = 64;
-    if (KK == 128) {
-        const size_t shm = (gemm::smem_bytes<T, 128, TN>()) + sizeof(T) * 128 * (TN + 1);
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void *)k_bt1_fused<T, 128>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)shm);
-            attr = true;
-        }
-        hipLaunchKernelGGL((k_bt1_fused<T, 128>), dim3(cdiv(ncols, TN)), dim3(256), shm, st, Z, ldz, r0, m, ncols, V1,
-                           b1, V2, m2, Tm);
-    } else {
-        const size_t shm = (gemm::smem_bytes<T, 128, TN>()) + sizeof(T) * 64 * (TN + 1);
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void *)k_bt1_fused<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)shm);
-            attr = true;
-        }
-        hipLaunchKernelGGL((k_bt1_fused<T, 64>), dim3(cdiv(ncols, TN)), dim3(256), shm, st, Z, ldz, r0, m, ncols, V1,
-                           b1, V2, m2, Tm);
-    }
+    const int tiles = (int)cdiv(ncols, 128);
+    int S = (int)cdiv(512, tiles > 0 ? tiles : 1);
+    const int maxS = (int)cdiv(m, 512);
+    if (S > maxS) S = maxS;
+    if (S > bt1_max_splits()) S = bt1_max_splits();
+    if (S < 1) S = 1;
+    return S;
+}
+
+template <typename T, int KK>
+static void bt1_block(T *Z, int ldz, int m, int ncols, MergedV<T> V, const double *Tm, double *Wp, T *W2,
+                      hipStream_t st)
+{
+    int S = bt1_splits(m, ncols);
+    const int kc = (int)(cdiv(cdiv(m, S), 16) * 16);
+    S = (int)cdiv(m, kc);
+    hipLaunchKernelGGL((k_bt1_w<T, KK>), dim3(cdiv(ncols, 128), S), dim3(256), (gemm::smem_bytes<T, KK, 128>()), st,
+                       (const T *)Z, ldz, ncols, V, kc, Wp);
+    hipLaunchKernelGGL((k_bt1_t<T, KK>), dim3(cdiv(ncols, 64)), dim3(256), (gemm::smem_bytes<T, KK, 64>()), st, Tm,
+                       (const double *)Wp, S, ncols, W2);
+    hipLaunchKernelGGL((k_bt1_z<T, KK>), dim3(cdiv(m, 128), cdiv(ncols, 64)), dim3(256),
+                       (gemm::smem_bytes<T, 128, 64>()), st, Z, ldz, ncols, V, (const T *)W2);
+}
+
+template <typename T>
+void launch_bt1_block(T *Z, int ldz, int r0, int m, int ncols, const T *V1, int b1, const T *V2, int m2,
+                      const double *Tm, int KK, double *Wp, T *W2, hipStream_t st)
+{
+    if (m <= 0 || ncols <= 0) return;
+    MergedV<T> V{V1, V2, b1, m, m2};
+    if (KK == 128) bt1_block<T, 128>(Z + r0, ldz, m, ncols, V, Tm, Wp, W2, st);
+    else if (KK == 64) bt1_block<T, 64>(Z + r0, ldz, m, ncols, V, Tm, Wp, W2, st);
+    else bt1_block<T, 32>(Z + r0, ldz, m, ncols, V, Tm, Wp, W2, st);
 }
 
 void launch_merge_t(const double *T1, const double *T2, const double *Gp, int S, int b, double *Tm, hipStream_t st)
@@ -773,10 +813,10 @@ void launch_merge_t(const double *T1, const double *T2, const double *Gp, int S,
     hipLaunchKernelGGL(k_merge_t, dim3(1), dim3(256), 0, st, T1, T2, Gp, S, b, Tm);
 }
 
-template void launch_bt1_fused<double>(double *, int, int, int, int, const double *, int, const double *, int,
-                                       const double *, int, hipStream_t);
-template void launch_bt1_fused<float>(float *, int, int, int, int, const float *, int, const float *, int,
-                                      const double *, int, hipStream_t);
+template void launch_bt1_block<double>(double *, int, int, int, int, const double *, int, const double *, int,
+                                       const double *, int, double *, double *, hipStream_t);
+template void launch_bt1_block<float>(float *, int, int, int, int, const float *, int, const float *, int,
+                                      const double *, int, double *, float *, hipStream_t);
 template void launch_dscale<double>(const double *, int, int, int, double *, int, hipStream_t);
 template void launch_dscale<float>(const double *, int, int, int, float *, int, hipStream_t);
 template void launch_bt2<double>(double *, int, int, int, int, int, const double *, const double *, double *,

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_panel_qr(T *__restrict__ W, int ldw, in
 // ---------------------------------------------------------------------------
 // Y0 partial (split s): rows [m0, m0+64) of  A_trail V  over k in [kb, ke).
 template <typename T, int TN>
-__global__ __launch_bounds__(256) void k_skew_symm(const T *__restrict__ W, int ldw, int r0, int m,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_skew_symm(const T *__restrict__ W, int ldw, int r0, int m,
                                                    const T *__restrict__ Vd, int B,
                                                    T *__restrict__ Ypart, int kchunk)
 {
@@ -235,7 +235,7 @@ __global__ void k_ysum(const T *__restrict__ Ypart, int S, size_t len, T *__rest
 
 // Partial V^T Y0 over row chunk blockIdx.x (rows [c*rc, (c+1)*rc)).
 template <typename T, int TB>
-__global__ __launch_bounds__(256) void k_gram(const T *__restrict__ Vd, const T *__restrict__ Y0,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_gram(const T *__restrict__ Vd, const T *__restrict__ Y0,
                                               int m, int B, int rc, double *__restrict__ Gp)
 {
     extern __shared__ char smraw[];
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) void k_small(const double *__restrict__ Gp, in
 
 // W = [Y0 V] Tx  (m x B)
 template <typename T, int TN>
-__global__ __launch_bounds__(256) void k_wform(const T *__restrict__ Y0, const T *__restrict__ Vd,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_wform(const T *__restrict__ Y0, const T *__restrict__ Vd,
                                                const T *__restrict__ Tx, int m, int B,
                                                T *__restrict__ Wd)
 {
@@ -329,7 +329,7 @@ __device__ __forceinline__ void tri_index(int t, int &I, int &J)
 }
 
 template <typename T, int TT>
-__global__ __launch_bounds__(256) void k_skew_syr2k(T *__restrict__ W, int ldw, int r0, int m,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_skew_syr2k(T *__restrict__ W, int ldw, int r0, int m,
                                                     const T *__restrict__ Vd, const T *__restrict__ Wd,
                                                     int B)
 {

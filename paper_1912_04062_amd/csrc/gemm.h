@@ -14,6 +14,10 @@
 #pragma once
 #include "common.h"
 
+// Register cap for kernels built on the engine: two wavefronts per SIMD, so
+// that one wave's LDS and global traffic overlaps the other's MFMAs.
+#define GEMM_OCC2 __attribute__((amdgpu_waves_per_eu(2, 8)))
+
 namespace gemm {
 
 constexpr int TK = 16;

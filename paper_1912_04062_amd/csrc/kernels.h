@@ -58,9 +58,14 @@ void launch_copy_cols(const T *src, int lds, T *dst, int ldd, int m, int ncol, h
 template <typename T>
 void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int ncol, hipStream_t st);
 
+// Stage-1 block Z[r0:r0+m, 0:ncols] -= V T V^T Z[r0:r0+m, :] for KK in {32, 64, 128}
+// reflectors (V = [V1, V2 shifted by b1 rows] when V2 is given).  Wp holds
+// bt1_max_splits() * KK * ncols doubles, W2 KK * ncols elements.
+constexpr int bt1_max_splits() { return 16; }
+int bt1_splits(int m, int ncols);
 template <typename T>
-void launch_bt1_fused(T *Z, int ldz, int r0, int m, int ncols, const T *V1, int b1, const T *V2, int m2,
-                      const double *Tm, int KK, hipStream_t st);
+void launch_bt1_block(T *Z, int ldz, int r0, int m, int ncols, const T *V1, int b1, const T *V2, int m2,
+                      const double *Tm, int KK, double *Wp, T *W2, hipStream_t st);
 void launch_merge_t(const double *T1, const double *T2, const double *Gp, int S, int b, double *Tm, hipStream_t st);
 
 // refine.hip

@@ -59,7 +59,7 @@ __global__ void k_split_x(const double *__restrict__ X, int n, int nev, int odd,
 
 // P = A X with A skew, read from its strict lower triangle (lda), FP64.
 template <int TM, int TN>
-__global__ __launch_bounds__(256) void k_skew_mm(const double *__restrict__ A, int lda, int n,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_skew_mm(const double *__restrict__ A, int lda, int n,
                                                  const double *__restrict__ X, int ncx, double *__restrict__ P)
 {
     extern __shared__ char smraw[];
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_skew_mm(const double *__restrict__ A, i
 
 // Lower tiles (I >= J) of S = X^T P and G = X^T X (both ncx x ncx, FP64).
 template <int TT>
-__global__ __launch_bounds__(256) void k_xtp_xtx(const double *__restrict__ X, const double *__restrict__ P, int n,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_xtp_xtx(const double *__restrict__ X, const double *__restrict__ P, int n,
                                                  int ncx, double *__restrict__ S, double *__restrict__ G)
 {
     extern __shared__ char smraw[];
@@ -251,7 +251,7 @@ __global__ void k_eform(const double *__restrict__ S, const double *__restrict__
 
 // Xn = X + X E  (ncx x ncx E), the product on the MFMA of type T.
 template <typename T, typename TE, int TM, int TN>
-__global__ __launch_bounds__(256) void k_xe(const double *__restrict__ X, const TE *__restrict__ E, int n, int ncx,
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_xe(const double *__restrict__ X, const TE *__restrict__ E, int n, int ncx,
                                             double *__restrict__ Xn)
 {
     extern __shared__ char smraw[];
@@ -297,8 +297,8 @@ void launch_split_x(const double *X, int n, int nev, int odd, double *Zr, int ld
 void launch_refine_products(const double *A, int lda, int n, const double *X, int ncx, double *P, double *S,
                             double *G, hipStream_t st)
 {
-    dim3 g1(cdiv(n, 128), cdiv(ncx, 128));
-    hipLaunchKernelGGL((k_skew_mm<128, 128>), g1, dim3(256), (gemm::smem_bytes<double, 128, 128>()), st, A, lda, n,
+    dim3 g1(cdiv(n, 128), cdiv(ncx, 64));
+    hipLaunchKernelGGL((k_skew_mm<128, 64>), g1, dim3(256), (gemm::smem_bytes<double, 128, 64>()), st, A, lda, n,
                        X, ncx, P);
     const int TT = 64;
     unsigned nt = cdiv(ncx, TT);
