@@ -221,205 +221,309 @@ __global__ __launch_bounds__(256) void k_bt2_apply(T *__restrict__ Z, int ldz, i
 // per pass of two sweep-blocks.
 //
 // A workgroup owns 64 columns; each wavefront keeps its 16-column strip of the
-// 256-row window in registers, in the MFMA result layout (row 16q + l/16 + 4r
-// of tile q, column l%16).  For the FP64 16x16x4 MFMA that layout is also the
-// B-operand layout of k-step 4r of the tile, so Z, W1 = V^T Z and W2 = T W1
-// never leave registers; V (as a 128 x 64 parallelogram) and T are in LDS.
-namespace bt2w {
+// 256-row window in registers, in the FP64 MFMA result layout (row
+// 16q + l/16 + 4r of tile q, column l%16), which is also the B-operand layout
+// of k-step 4r of the tile, so Z, W1 = V^T Z and W2 = T W1 never leave
+// registers.  The window's slots are kept in positional order (slot j = row
+// block s_hi + tau - 2 + j) by rotating registers when it slides, so group
+// (s_hi, tau) always uses slots 2, 3 and group (s_hi - 1, tau - 1) slots 0, 1.
+// Each wavefront owns its columns for the whole kernel, so Z moves directly
+// between global memory and registers (the block entering the window is
+// loaded one step ahead).  V and T (64 x 64 each, compact as in memory) are
+// double-buffered in LDS and filled by 16-byte global-to-LDS loads one group
+// ahead; one barrier per group.
+namespace bt2p {
 
-constexpr int B = 64, LDP = 65;
+constexpr int B = 64;
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void gbl_void;
 
 struct Win {
     d4 z[4][4];      // [slot][row tile]
 };
 
-__device__ __forceinline__ bool blk_valid(int x, int n) { return x >= 0 && 1 + 64 * x < n; }
+// Group cursor: pass sh (sweep-blocks sh and sh - 1), time tau, w = 0 for
+// group (sh, tau) and w = 1 for group (sh - 1, tau - 1).  sh < 0: done.
+struct Cur {
+    int sh, tau, w;
+};
 
-// global rows of block x (64 x 64 of this workgroup's columns) -> slot, via LDS
-template <int SL>
-__device__ __forceinline__ void load_block(Win &w, const double *__restrict__ Z, int ldz, int n, int col0, int ncl,
-                                           int x, double *St)
+__device__ __forceinline__ int ngr(const int *goff, int sg) { return goff[sg + 1] - goff[sg]; }
+
+__device__ __forceinline__ int taumax(const int *goff, int sh)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    __syncthreads();
-    const bool ok = blk_valid(x, n);
-    const int r0 = 1 + 64 * x;
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-        const int e = tid + 256 * p;
-        const int r = e & 63, c = e >> 6;
-        double v = 0.0;
-        if (ok && r0 + r < n && c < ncl) v = Z[(size_t)(col0 + c) * ldz + r0 + r];
-        St[r * LDP + c] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-            w.z[SL][q][rr] = St[(16 * q + (lane >> 4) + 4 * rr) * LDP + 16 * wv + (lane & 15)];
+    int t = ngr(goff, sh) - 1;
+    if (sh >= 1) t = max(t, ngr(goff, sh - 1));
+    return t;
 }
 
-template <int SL>
-__device__ __forceinline__ void store_block(const Win &w, double *__restrict__ Z, int ldz, int n, int col0, int ncl,
-                                            int x, double *St)
+__device__ __forceinline__ bool cvalid(const Cur &c, const int *goff)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (!blk_valid(x, n)) return;            // uniform across the workgroup
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-            St[(16 * q + (lane >> 4) + 4 * rr) * LDP + 16 * wv + (lane & 15)] = w.z[SL][q][rr];
-    __syncthreads();
-    const int r0 = 1 + 64 * x;
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-        const int e = tid + 256 * p;
-        const int r = e & 63, c = e >> 6;
-        if (r0 + r < n && c < ncl) Z[(size_t)(col0 + c) * ldz + r0 + r] = St[r * LDP + c];
+    if (c.w == 0) return c.tau < ngr(goff, c.sh);
+    return c.sh >= 1 && c.tau >= 1 && c.tau - 1 < ngr(goff, c.sh - 1);
+}
+
+__device__ __forceinline__ void advance(Cur &c, const int *goff)
+{
+    while (c.sh >= 0) {
+        if (c.w == 0) {
+            c.w = 1;
+        } else {
+            c.w = 0;
+            if (++c.tau > taumax(goff, c.sh)) {
+                c.sh -= 2;
+                c.tau = 0;
+                if (c.sh < 0) return;
+            }
+        }
+        if (cvalid(c, goff)) return;
     }
 }
 
-// Apply group g to the row blocks in slots S0 (upper) and S1 (lower).
+__device__ __forceinline__ size_t gid(const Cur &c, const int *goff)
+{
+    return (c.w == 0) ? (size_t)goff[c.sh] + c.tau : (size_t)goff[c.sh - 1] + c.tau - 1;
+}
+
+// V then T of group g (32 KB each) into Vl / Tl: wave w moves 1 KB chunks
+// 16w .. 16w + 15 (chunks 0..31 are V, 32..63 are T), 16 bytes per lane.
+__device__ __forceinline__ void prefetch(const double *__restrict__ V2, const double *__restrict__ T2, size_t g,
+                                         double *Vl, double *Tl)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const double *src = (wv < 2) ? V2 + g * (B * B) : T2 + g * (B * B);
+    double *dst = (wv < 2) ? Vl : Tl;
+    const int c0 = (wv & 1) * 16;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        __builtin_amdgcn_global_load_lds((gbl_void *)(src + (size_t)(c0 + j) * 128 + 2 * lane),
+                                         (lds_void *)(dst + (c0 + j) * 128), 16, 0, 0);
+}
+
+__device__ __forceinline__ bool blk_ok(int x, int n) { return x >= 0 && 1 + 64 * x < n; }
+
+// Row block x (64 rows from 1 + 64x) of this wavefront's 16 columns, in the
+// MFMA result layout.  Every load is issued unconditionally, clamped to a
+// valid address, and nothing waits for it until the block is used: rows past
+// n and columns past ncols hold copies of valid (finite) entries, which only
+// ever meet zero reflector entries and are never stored.
+__device__ __forceinline__ void load_block(d4 (&zb)[4], const double *__restrict__ Z, int ldz, int n, int col0,
+                                           int ncl, int x)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (!blk_ok(x, n)) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) zb[q] = (d4){0.0, 0.0, 0.0, 0.0};
+        return;
+    }
+    const int c = 16 * wv + (lane & 15);
+    const int r0 = 1 + 64 * x;
+    const double *zc = Z + (size_t)(col0 + (c < ncl ? c : 0)) * ldz;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int r = r0 + 16 * q + (lane >> 4) + 4 * rr;
+            zb[q][rr] = zc[r < n ? r : n - 1];
+        }
+}
+
+__device__ __forceinline__ void store_block(const d4 (&zb)[4], double *__restrict__ Z, int ldz, int n, int col0,
+                                            int ncl, int x)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = 16 * wv + (lane & 15);
+    if (!blk_ok(x, n) || c >= ncl) return;
+    const int r0 = 1 + 64 * x;
+    double *zc = Z + (size_t)(col0 + c) * ldz;
+    if (r0 + 63 < n) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) zc[r0 + 16 * q + (lane >> 4) + 4 * rr] = zb[q][rr];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int r = r0 + 16 * q + (lane >> 4) + 4 * rr;
+                if (r < n) zc[r] = zb[q][rr];
+            }
+    }
+}
+
+// Z[slots S0, S1] <- (I - Vp T Vp^T) Z[slots S0, S1]; Vp is the 128 x 64
+// parallelogram Vp[r][i] = V[r - i][i] (0 <= r - i < 64), V compact in Vl
+// (V[d][i] at 64 i + d, with VPAD readable elements on both sides), T compact
+// in Tl (T[i][u] at 64 u + i).
+//
+// Every LDS operand address is a per-lane base plus a compile-time offset,
+// and the parallelogram test is a compare of a per-lane constant with a
+// compile-time bound; the per-lane constants are re-derived at each call so
+// that the compiler does not keep hundreds of hoisted addresses and masks
+// alive across the group loop.  Each phase runs its k-steps outermost so that
+// MFMAs of independent output tiles follow each other, and loads the LDS
+// operands of a chunk of k-steps before the chunk's MFMAs.
+constexpr int VPAD = 96;
+
 template <int S0, int S1>
-__device__ __forceinline__ void apply_group(Win &w, const double *__restrict__ V2, const double *__restrict__ T2,
-                                            size_t g, double *Vp, double *Ts)
+__device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl)
 {
-    const int tid = threadIdx.x, lane = tid & 63;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
     const int lr = lane & 15, lk = lane >> 4;
-    // parallelogram Vp[d + i][i] = V[d][i] (its zero part is set once per
-    // kernel) and Ts[u][i] = T[i][u]; all global loads issued first
-    const double *Vg = V2 + g * (size_t)(B * B);
-    const double *Tg = T2 + g * (size_t)(B * B);
-    double vv[16], tt[16];
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-        const int e = tid + 256 * p;
-        vv[p] = Vg[e];
-        tt[p] = Tg[e];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-        const int e = tid + 256 * p;
-        const int d = e & 63, i = e >> 6;       // V is column-major b x nb2
-        Vp[(d + i) * LDP + i] = vv[p];
-        Ts[(e >> 6) * LDP + (e & 63)] = tt[p];
-    }
-    __syncthreads();
-    // W1 = Vp^T Zg   (4 row tiles over i; K = 128 rows of the two slots)
+    // W1 = Vp^T Zg: element (i = 16mt + lr, r = 4ks + lk) at 63 lr + lk + (1008 mt + 4 ks),
+    // inside the parallelogram when 0 <= lk - lr + 4ks - 16mt < 64
+    const double *vb1 = Vl + 63 * lr + lk;
+    const int dw = lk - lr;
     d4 w1[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int mt = 0; mt < 4; ++mt) w1[mt] = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < 32; ++ks) {          // k-step over rows r4 = 4 ks
-            if (ks < 4 * mt || ks >= 4 * mt + 20) continue;   // outside the parallelogram
-            const int r4 = 4 * ks;
-            const double a = Vp[(r4 + lk) * LDP + 16 * mt + lr];
-            const int tile = ks >> 2, rr = ks & 3;   // tile of 16 rows within the 128
-            const double bz = (tile < 4) ? w.z[S0][tile & 3][rr] : w.z[S1][tile & 3][rr];
-            acc = mfma_16x16x4(a, bz, acc);
+    for (int kc = 0; kc < 32; kc += 4) {
+        double a[4][4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int ks = kc + kk;
+                if (ks >= 4 * mt && ks < 4 * mt + 20) {
+                    const double x = vb1[1008 * mt + 4 * ks];
+                    const int d = dw + 4 * ks - 16 * mt;
+                    a[kk][mt] = ((unsigned)d < (unsigned)B) ? x : 0.0;
+                } else {
+                    a[kk][mt] = 0.0;
+                }
+            }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int ks = kc + kk;
+            const double bz = (ks < 16) ? w.z[S0][ks >> 2][ks & 3] : w.z[S1][(ks >> 2) & 3][ks & 3];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                if (ks >= 4 * mt && ks < 4 * mt + 20) w1[mt] = mfma_16x16x4(a[kk][mt], bz, w1[mt]);
         }
-        w1[mt] = acc;
     }
-    // W2 = T W1   (T upper triangular)
+    // W2 = T W1 (T upper triangular): T[16mt + lr][4ks + lk] at 64 lk + lr + (256 ks + 16 mt)
+    const double *tb = Tl + 64 * lk + lr;
     d4 w2[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int mt = 0; mt < 4; ++mt) w2[mt] = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            if (ks < 4 * mt) continue;
-            const double a = Ts[(4 * ks + lk) * LDP + 16 * mt + lr];
-            acc = mfma_16x16x4(a, w1[ks >> 2][ks & 3], acc);
+    for (int kc = 0; kc < 16; kc += 4) {
+        double a[4][4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int ks = kc + kk;
+                a[kk][mt] = (ks >= 4 * mt) ? tb[256 * ks + 16 * mt] : 0.0;
+            }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int ks = kc + kk;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                if (ks >= 4 * mt) w2[mt] = mfma_16x16x4(a[kk][mt], w1[ks >> 2][ks & 3], w2[mt]);
         }
-        w2[mt] = acc;
     }
-    // Zg -= Vp W2   (8 row tiles of the two slots; K = 64 over i)
+    // Zg -= Vp W2: element (r = 16rt + lr, i = 4ks + lk) at 63 lk + lr + (252 ks + 16 rt),
+    // inside when 0 <= lr - lk + 16rt - 4ks < 64
+    const double *vb3 = Vl + 63 * lk + lr;
+    const int dz = lr - lk;
 #pragma unroll
-    for (int rt = 0; rt < 8; ++rt) {
-        d4 acc = (rt < 4) ? w.z[S0][rt & 3] : w.z[S1][rt & 3];
+    for (int kc = 0; kc < 16; kc += 2) {
+        double a[2][8];
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {          // i4 = 4 ks
-            const int i4 = 4 * ks;
-            if (i4 + 3 < 16 * rt - B + 1 || i4 >= 16 * rt + 16) continue;
-            const double a = -Vp[(16 * rt + lr) * LDP + i4 + lk];
-            acc = mfma_16x16x4(a, w2[ks >> 2][ks & 3], acc);
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt) {
+                const int ks = kc + kk, i4 = 4 * ks;
+                if (!(i4 + 3 < 16 * rt - B + 1 || i4 >= 16 * rt + 16)) {
+                    const double x = vb3[252 * ks + 16 * rt];
+                    const int d = dz + 16 * rt - 4 * ks;
+                    a[kk][rt] = ((unsigned)d < (unsigned)B) ? -x : 0.0;
+                } else {
+                    a[kk][rt] = 0.0;
+                }
+            }
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int ks = kc + kk, i4 = 4 * ks;
+            const double bw = w2[ks >> 2][ks & 3];
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt) {
+                if (i4 + 3 < 16 * rt - B + 1 || i4 >= 16 * rt + 16) continue;
+                if (rt < 4) w.z[S0][rt] = mfma_16x16x4(a[kk][rt], bw, w.z[S0][rt]);
+                else w.z[S1][rt - 4] = mfma_16x16x4(a[kk][rt], bw, w.z[S1][rt - 4]);
+            }
         }
-        if (rt < 4) w.z[S0][rt & 3] = acc;
-        else w.z[S1][rt & 3] = acc;
     }
 }
 
-__device__ __forceinline__ int ngroups_of(const int *goff, int sg) { return goff[sg + 1] - goff[sg]; }
-
-// One time step tau (tau % 4 == P) of a pass with top sweep-block sh.
-template <int P>
-__device__ __forceinline__ void tau_step(Win &w, double *__restrict__ Z, int ldz, int n, int col0, int ncl,
-                                         const double *__restrict__ V2, const double *__restrict__ T2,
-                                         const int *__restrict__ goff, int sh, bool two, int tau, double *Vp,
-                                         double *Ts, double *St)
-{
-    constexpr int SNEW = (P + 3) & 3;
-    if (tau > 0) {
-        store_block<SNEW>(w, Z, ldz, n, col0, ncl, sh + tau - 3, St);
-        load_block<SNEW>(w, Z, ldz, n, col0, ncl, sh + tau + 1, St);
-    }
-    if (tau < ngroups_of(goff, sh))
-        apply_group<(P + 2) & 3, (P + 3) & 3>(w, V2, T2, (size_t)goff[sh] + tau, Vp, Ts);
-    if (two && tau >= 1 && tau - 1 < ngroups_of(goff, sh - 1))
-        apply_group<P & 3, (P + 1) & 3>(w, V2, T2, (size_t)goff[sh - 1] + tau - 1, Vp, Ts);
-}
-
-template <int SL>
-__device__ __forceinline__ void store_final(const Win &w, double *Z, int ldz, int n, int col0, int ncl, int sh,
-                                            int taum, double *St)
-{
-    const int x = sh + taum - 2 + ((SL - taum) & 3);
-    store_block<SL>(w, Z, ldz, n, col0, ncl, x, St);
-}
-
-}  // namespace bt2w
+}  // namespace bt2p
 
 __global__ __launch_bounds__(256) void k_bt2_win(double *__restrict__ Z, int ldz, int n, int ncols,
-                                                 const double *__restrict__ V2, const double *__restrict__ T2,
-                                                 const int *__restrict__ goff, int nsig)
+                                                const double *__restrict__ V2, const double *__restrict__ T2,
+                                                const int *__restrict__ goff, int nsig)
 {
-    using namespace bt2w;
+    using namespace bt2p;
     extern __shared__ double lds[];
-    double *Vp = lds;                    // 128 x 65
-    double *Ts = Vp + 128 * LDP;         // 64 x 65
-    double *St = Ts + 64 * LDP;          // 64 x 65
+    // buffer q: V (with VPAD readable doubles before and after), then T
+    constexpr int BUF = VPAD + B * B + VPAD + B * B;
+    auto Vl = [&](int q) -> double * { return lds + q * BUF + VPAD; };
+    auto Tl = [&](int q) -> double * { return lds + q * BUF + VPAD + B * B + VPAD; };
     const int col0 = blockIdx.x * 64;
     const int ncl = min(64, ncols - col0);
-    // zero part of the parallelogram (the same for every group)
-    for (int e = threadIdx.x; e < 128 * 64; e += 256) {
-        const int r = e >> 6, i = e & 63, d = r - i;
-        if (d < 0 || d >= B) Vp[r * LDP + i] = 0.0;
-    }
+    if (nsig <= 0) return;
+    Cur c{nsig - 1, 0, 0};
+    if (!cvalid(c, goff)) advance(c, goff);
+    if (c.sh < 0) return;
+    prefetch(V2, T2, gid(c, goff), Vl(0), Tl(0));
+    Cur nx = c;
+    advance(nx, goff);
     Win w;
-    for (int sh = nsig - 1; sh >= 0; sh -= 2) {
-        const bool two = sh >= 1;
-        int taum = ngroups_of(goff, sh) - 1;
-        if (two) taum = max(taum, ngroups_of(goff, sh - 1));
-        load_block<0>(w, Z, ldz, n, col0, ncl, sh - 2, St);
-        load_block<1>(w, Z, ldz, n, col0, ncl, sh - 1, St);
-        load_block<2>(w, Z, ldz, n, col0, ncl, sh, St);
-        load_block<3>(w, Z, ldz, n, col0, ncl, sh + 1, St);
-        for (int tau = 0; tau <= taum; tau += 4) {
-            tau_step<0>(w, Z, ldz, n, col0, ncl, V2, T2, goff, sh, two, tau, Vp, Ts, St);
-            if (tau + 1 <= taum) tau_step<1>(w, Z, ldz, n, col0, ncl, V2, T2, goff, sh, two, tau + 1, Vp, Ts, St);
-            if (tau + 2 <= taum) tau_step<2>(w, Z, ldz, n, col0, ncl, V2, T2, goff, sh, two, tau + 2, Vp, Ts, St);
-            if (tau + 3 <= taum) tau_step<3>(w, Z, ldz, n, col0, ncl, V2, T2, goff, sh, two, tau + 3, Vp, Ts, St);
+    d4 nxt[4];                                     // the block that enters the window next
+    int cur_sh = c.sh, cur_tau = 0, buf = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) load_block(w.z[j], Z, ldz, n, col0, ncl, cur_sh - 2 + j);
+    load_block(nxt, Z, ldz, n, col0, ncl, cur_sh + 2);
+    wait_vmem();
+    __syncthreads();
+    while (c.sh >= 0) {
+        if (c.sh != cur_sh) {                      // next pass: flush the window, load the new one
+#pragma unroll
+            for (int j = 0; j < 4; ++j) store_block(w.z[j], Z, ldz, n, col0, ncl, cur_sh + cur_tau - 2 + j);
+            cur_sh = c.sh;
+            cur_tau = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) load_block(w.z[j], Z, ldz, n, col0, ncl, cur_sh - 2 + j);
+            load_block(nxt, Z, ldz, n, col0, ncl, cur_sh + 2);
         }
-        store_final<0>(w, Z, ldz, n, col0, ncl, sh, taum, St);
-        store_final<1>(w, Z, ldz, n, col0, ncl, sh, taum, St);
-        store_final<2>(w, Z, ldz, n, col0, ncl, sh, taum, St);
-        store_final<3>(w, Z, ldz, n, col0, ncl, sh, taum, St);
+        while (cur_tau < c.tau) {                  // slide down one block
+            store_block(w.z[0], Z, ldz, n, col0, ncl, cur_sh + cur_tau - 2);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                w.z[0][q] = w.z[1][q];
+                w.z[1][q] = w.z[2][q];
+                w.z[2][q] = w.z[3][q];
+                w.z[3][q] = nxt[q];
+            }
+            ++cur_tau;
+            load_block(nxt, Z, ldz, n, col0, ncl, cur_sh + cur_tau + 2);
+        }
+        if (nx.sh >= 0) prefetch(V2, T2, gid(nx, goff), Vl(buf ^ 1), Tl(buf ^ 1));
+        if (c.w == 0) apply<2, 3>(w, Vl(buf), Tl(buf));
+        else apply<0, 1>(w, Vl(buf), Tl(buf));
+        wait_vmem();
+        __syncthreads();
+        buf ^= 1;
+        c = nx;
+        advance(nx, goff);
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) store_block(w.z[j], Z, ldz, n, col0, ncl, cur_sh + cur_tau - 2 + j);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,49 +624,56 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_bt1_z(
 }
 
 // Merged T of two consecutive panels: Tm = [[T1, -T1 G T2], [0, T2]] with
-// G = sum of the partial products V1(b:, :)^T V2 (b x b each).
+// G = sum of the partial products V1(b:, :)^T V2 (b x b each, b <= 64).
 __global__ __launch_bounds__(256) void k_merge_t(const double *__restrict__ T1, const double *__restrict__ T2,
                                                  const double *__restrict__ Gp, int S, int b,
                                                  double *__restrict__ Tm)
 {
-    __shared__ double G[64 * 65], M1[64 * 65];
-    const int tid = threadIdx.x, bb = b * b, K = 2 * b;
+    __shared__ double G[64 * 65], M1[64 * 65], A1[64 * 65], A2[64 * 65];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6, K = 2 * b;
+    auto off = [=](int i, int j) -> int { return (i < b && j < b) ? j * b + i : -1; };
     {
-        double acc[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-        for (int p = 0; p < S; ++p)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int e = tid + 256 * q;
-                if (e < bb) acc[q] += Gp[(size_t)p * bb + e];
-            }
+        double acc[16], t1[16], t2[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int e = tid + 256 * q;
-            if (e < bb) G[(e % b) * 65 + e / b] = acc[q];        // G[u][v]
+            const int o = off(tx, ty + 4 * q);
+            t1[q] = (o >= 0) ? T1[o] : 0.0;
+            t2[q] = (o >= 0) ? T2[o] : 0.0;
+        }
+        sum_partials_2d(Gp, S, (size_t)b * b, off, acc);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = ty + 4 * q;
+            G[tx * 65 + j] = acc[q];                 // G[u][v]
+            A1[tx * 65 + j] = t1[q];                 // T1[i][u]
+            A2[tx * 65 + j] = t2[q];                 // T2[w][v]
         }
     }
     __syncthreads();
-    for (int e = tid; e < bb; e += 256) {            // M1 = G T2
-        const int u = e % b, v = e / b;
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {                   // M1 = G T2 (T2 upper)
+        const int v = ty + 4 * q;
         double s = 0.0;
-        for (int w = 0; w <= v; ++w) s += G[u * 65 + w] * T2[(size_t)v * b + w];
-        M1[u * 65 + v] = s;
+        for (int w = 0; w <= v && w < b; ++w) s += G[tx * 65 + w] * A2[w * 65 + v];
+        M1[tx * 65 + v] = s;
     }
     __syncthreads();
-    for (int e = tid; e < K * K; e += 256) {
-        const int i = e % K, j = e / K;
-        double val = 0.0;
-        if (i < b && j < b) val = T1[(size_t)j * b + i];
-        else if (i >= b && j >= b) val = T2[(size_t)(j - b) * b + (i - b)];
-        else if (i < b && j >= b) {
-            double s = 0.0;
-            for (int u = i; u < b; ++u) s += T1[(size_t)u * b + i] * M1[u * 65 + (j - b)];
-            val = -s;
-        }
-        Tm[e] = val;
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {                   // T12 = -T1 M1 (T1 upper), into G
+        const int j = ty + 4 * q;
+        double s = 0.0;
+        for (int u = tx; u < b; ++u) s += A1[tx * 65 + u] * M1[u * 65 + j];
+        G[tx * 65 + j] = -s;
     }
+    __syncthreads();
+    for (int j = ty; j < K; j += 4)
+        for (int i = tx; i < K; i += 64) {
+            double val = 0.0;
+            if (i < b && j < b) val = A1[i * 65 + j];
+            else if (i >= b && j >= b) val = A2[(i - b) * 65 + (j - b)];
+            else if (i < b) val = G[i * 65 + (j - b)];
+            Tm[(size_t)j * K + i] = val;
+        }
 }
 
 // Cpart[s] = A[kb:ke, 0:M]^T B[kb:ke, 0:N]   (A: K x M, B: K x N, column-major)
@@ -663,6 +774,13 @@ __global__ void k_copy_cols(const T *__restrict__ src, int lds, T *__restrict__ 
         dst[(size_t)c * ldd + i] = src[(size_t)c * lds + i];
 }
 
+__global__ void k_to_float(const double *__restrict__ src, int lds, float *__restrict__ dst, int ldd, int m)
+{
+    const int c = blockIdx.y;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256)
+        dst[(size_t)c * ldd + i] = (float)src[(size_t)c * lds + i];
+}
+
 template <typename T>
 __global__ void k_to_double(const T *__restrict__ src, int lds, double *__restrict__ dst, int ldd, int m)
 {
@@ -691,7 +809,7 @@ void launch_bt2(T *Z, int ldz, int n, int ncols, int b, int nb2, const double *V
     hipLaunchKernelGGL(k_bt2_tfac<T>, dim3(ngroups), dim3(256), 0, st, V2, tau2, b, nb2, T2, V2t);
     const T *Vuse = V2t ? (const T *)V2t : (const T *)(const void *)V2;
     if (sizeof(T) == sizeof(double) && b == 64 && nb2 == 64) {
-        const size_t shm = sizeof(double) * (size_t)(128 + 64 + 64) * bt2w::LDP;
+        const size_t shm = sizeof(double) * 2 * (2 * bt2p::VPAD + 2 * 64 * 64);
         static bool attr = false;
         if (!attr) {
             (void)hipFuncSetAttribute((const void *)k_bt2_win, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -767,6 +885,13 @@ void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int nc
     if (m <= 0 || ncol <= 0) return;
     hipLaunchKernelGGL(k_to_double<T>, dim3(cdiv(m, 256) > 8 ? 8 : cdiv(m, 256), ncol), dim3(256), 0, st, src, lds,
                        dst, ldd, m);
+}
+
+void launch_to_float(const double *src, int lds, float *dst, int ldd, int m, int ncol, hipStream_t st)
+{
+    if (m <= 0 || ncol <= 0) return;
+    hipLaunchKernelGGL(k_to_float, dim3(cdiv(m, 256) > 8 ? 8 : cdiv(m, 256), ncol), dim3(256), 0, st, src, lds, dst,
+                       ldd, m);
 }
 
 // Split of the row range of k_bt1_w: about two workgroups per CU, chunks of

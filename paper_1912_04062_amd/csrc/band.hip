@@ -257,41 +257,41 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_small(const double *__restrict__ Gp, int nchunk, int B,
                                                const double *__restrict__ Tf, T *__restrict__ Tx)
 {
-    __shared__ double G[64 * 64], Tm[64 * 64], M1[64 * 64];
-    const int tid = threadIdx.x, BB = B * B;
+    __shared__ double G[64 * 65], Tm[64 * 65], M1[64 * 65];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    auto off = [=](int i, int j) -> int { return (i < B && j < B) ? j * B + i : -1; };
     {
-        double acc[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-        for (int c = 0; c < nchunk; ++c)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int e = tid + 256 * q;
-                if (e < BB) acc[q] += Gp[(size_t)c * BB + e];
-            }
+        double acc[16], tf[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int e = tid + 256 * q;
-            if (e < BB) {
-                G[e] = acc[q];
-                Tm[e] = Tf[e];
-            }
+            const int o = off(tx, ty + 4 * q);
+            tf[q] = (o >= 0) ? Tf[o] : 0.0;
+        }
+        sum_partials_2d(Gp, nchunk, (size_t)B * B, off, acc);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            G[tx * 65 + ty + 4 * q] = acc[q];        // G[i][u]
+            Tm[tx * 65 + ty + 4 * q] = tf[q];        // T[u][j]
         }
     }
     __syncthreads();
-    for (int e = tid; e < BB; e += 256) {       // M1 = G T
-        int i = e % B, j = e / B;
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {                   // M1 = G T (T upper)
+        const int j = ty + 4 * q;
         double s = 0.0;
-        for (int u = 0; u <= j; ++u) s += G[u * B + i] * Tm[j * B + u];
-        M1[e] = s;
+        for (int u = 0; u <= j && u < B; ++u) s += G[tx * 65 + u] * Tm[u * 65 + j];
+        M1[tx * 65 + j] = s;
     }
     __syncthreads();
-    for (int e = tid; e < BB; e += 256) {       // X = T^T M1
-        int i = e % B, j = e / B;
-        double s = 0.0;
-        for (int u = 0; u <= i; ++u) s += Tm[i * B + u] * M1[j * B + u];
-        Tx[(size_t)j * 2 * B + i] = (T)Tm[e];
-        Tx[(size_t)j * 2 * B + B + i] = (T)(-0.5 * s);
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {                   // X = T^T M1
+        const int j = ty + 4 * q;
+        if (tx < B && j < B) {
+            double s = 0.0;
+            for (int u = 0; u <= tx; ++u) s += Tm[u * 65 + tx] * M1[u * 65 + j];
+            Tx[(size_t)j * 2 * B + tx] = (T)Tm[tx * 65 + j];
+            Tx[(size_t)j * 2 * B + B + tx] = (T)(-0.5 * s);
+        }
     }
 }
 

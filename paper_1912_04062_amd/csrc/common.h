@@ -138,6 +138,43 @@ __device__ __forceinline__ bool grid_sync(unsigned *ctr, unsigned target, unsign
     return gs_ok != 0;
 }
 
+// Sums of np partial arrays (stride pst) for the 16 elements a thread owns in
+// a 64 x 64 block: thread (tx, ty) = (tid % 64, tid / 64) owns row tx and
+// columns ty + 4q; off(i, j) < 0 marks an element outside the array.  The
+// loads of four partials are issued together; the summation order over p is
+// sequential, so the result does not depend on the batching.
+template <class OFF>
+__device__ __forceinline__ void sum_partials_2d(const double *__restrict__ P, int np, size_t pst, const OFF &off,
+                                                double acc[16])
+{
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    int o[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        o[q] = off(tx, ty + 4 * q);
+        acc[q] = 0.0;
+    }
+    int p = 0;
+    for (; p + 4 <= np; p += 4) {
+        double t[4][16];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) t[u][q] = (o[q] >= 0) ? P[(size_t)(p + u) * pst + o[q]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] += t[u][q];
+    }
+    for (; p < np; ++p) {
+        double t[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t[q] = (o[q] >= 0) ? P[(size_t)p * pst + o[q]] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += t[q];
+    }
+}
+
 // Wavefront sum (64 lanes) via cross-lane shuffles.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)

@@ -55,6 +55,7 @@ void launch_reduce_left(const double *S0, const double *Cpart, int S, int M, int
                         hipStream_t st);
 template <typename T>
 void launch_copy_cols(const T *src, int lds, T *dst, int ldd, int m, int ncol, hipStream_t st);
+void launch_to_float(const double *src, int lds, float *dst, int ldd, int m, int ncol, hipStream_t st);
 template <typename T>
 void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int ncol, hipStream_t st);
 

@@ -262,59 +262,66 @@ __global__ void k_transpose(const double *__restrict__ Y, int n, int nev, double
 }
 
 // Cholesky of G = sum of partials (NB x NB, NB <= 64) and R^{-1} (upper).
+// Thread (tx, ty) = (tid % 64, tid / 64) owns row tx and columns ty + 4q.
 __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp, int nparts, int NB,
                                                   double *__restrict__ Rinv)
 {
-    __shared__ double G[64 * 65], R[64 * 65];
-    const int tid = threadIdx.x;
+    __shared__ double G[64 * 65], R[64 * 65], part[4][64];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     {
-        // 16 independent sums per thread: the loads of one partial are issued together
         double acc[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-        for (int p = 0; p < nparts; ++p)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int e = tid + 256 * q;
-                if (e < NB * NB) acc[q] += Gp[(size_t)p * NB * NB + e];
-            }
+        sum_partials_2d(Gp, nparts, (size_t)NB * NB,
+                        [=](int i, int j) -> int { return (i < NB && j < NB) ? j * NB + i : -1; }, acc);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int e = tid + 256 * q;
-            if (e < NB * NB) G[(e % NB) * 65 + e / NB] = acc[q];   // G[i][j]
+            G[tx * 65 + ty + 4 * q] = acc[q];        // G[i][j]
+            R[tx * 65 + ty + 4 * q] = 0.0;
         }
     }
-    for (int e = tid; e < 64 * 65; e += 256) R[e] = 0.0;
     __syncthreads();
-    // G = R^T R, R upper; column-by-column (right-looking on G)
+    // G = R^T R, R upper (kept in the upper triangle of G), right-looking
     for (int j = 0; j < NB; ++j) {
-        if (tid == 0) {
-            double d = G[j * 65 + j];
-            G[j * 65 + j] = sqrt(d > 0.0 ? d : 1e-300);
+        const double d = G[j * 65 + j];
+        const double rjj = sqrt(d > 0.0 ? d : 1e-300);
+        // row j of R, read before the barrier by every thread
+        const double rjr = (tx > j) ? G[j * 65 + tx] / rjj : 0.0;
+        double rjc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = ty + 4 * q;
+            rjc[q] = (c > j && c < NB) ? G[j * 65 + c] / rjj : 0.0;
         }
         __syncthreads();
-        const double rjj = G[j * 65 + j];
-        if (tid > j && tid < NB) G[j * 65 + tid] /= rjj;      // row j of R
-        __syncthreads();
-        for (int e = tid; e < NB * NB; e += 256) {
-            int r = e / NB, c = e % NB;
-            if (r > j && c >= r) G[r * 65 + c] -= G[j * 65 + r] * G[j * 65 + c];
+        if (ty == 0) {
+            if (tx == j) G[j * 65 + j] = rjj;
+            else if (tx > j && tx < NB) G[j * 65 + tx] = rjr;
+        }
+        if (tx > j && tx < NB) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int c = ty + 4 * q;
+                if (c >= tx && c < NB) G[tx * 65 + c] -= rjr * rjc[q];
+            }
         }
         __syncthreads();
     }
-    // invert the upper triangular R (row-major in G): column c of R^{-1}
-    if (tid < NB) {
-        const int c = tid;
-        for (int i = NB - 1; i >= 0; --i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int u = i + 1; u <= c; ++u) s -= G[i * 65 + u] * R[u * 65 + c];
-            R[i * 65 + c] = (i <= c) ? s / G[i * 65 + i] : 0.0;
+    // R^{-1} by rows from the bottom: X[i][c] = (delta_ic - sum_{u>i} R[i][u] X[u][c]) / R[i][i];
+    // column c = tx, the sum over u split over the four waves
+    for (int i = NB - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int u = i + 1 + ty; u <= tx && u < NB; u += 4) s += G[i * 65 + u] * R[u * 65 + tx];
+        part[ty][tx] = s;
+        __syncthreads();
+        if (ty == 0 && tx < NB) {
+            const double tot = part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx];
+            R[i * 65 + tx] = (i <= tx) ? (((i == tx) ? 1.0 : 0.0) - tot) / G[i * 65 + i] : 0.0;
         }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-        int i = e % NB, j = e / NB;
-        Rinv[e] = R[i * 65 + j];          // column-major
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int j = ty + 4 * q;
+        if (tx < NB && j < NB) Rinv[(size_t)j * NB + tx] = R[tx * 65 + j];   // column-major
     }
 }
 
