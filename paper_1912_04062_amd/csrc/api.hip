@@ -70,7 +70,7 @@ namespace {
 // Workspace layout.  Offsets are 256-byte aligned.
 struct Layout {
     size_t W, Vall, Tall, tauall, Ypart, Y0, Wd, Gp, Tx, part, ab, goff, V2, tau2, T2, V2t, alpha, a2, stats,
-        lam, U0, U1, U2, Lm, Sw, Yiv, Qd, Z, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
+        lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, Qd, Z, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
         rstat, Tm, total;
     std::vector<size_t> Voff;
 };
@@ -125,6 +125,7 @@ Layout plan_layout(const Plan &p)
     L.Lm = take(sizeof(double) * n * nev);
     L.Sw = take(n * nev);
     L.Yiv = take(sizeof(double) * n * nev);
+    L.ivfac = take(sizeof(double) * 2 * nev);
     L.Qd = take(sizeof(double) * n * nev);
     L.Z = take(es * n * 2 * nev);
     L.Wp = take(sizeof(double) * tn_parts_max() * b * 2 * nev);
@@ -391,7 +392,8 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
     skew::launch_tridiag_eigvals(alpha, n, n / 2, nev, ptr<double>(h, L.a2), ptr<double>(h, L.stats), lam, st);
     skew::launch_tridiag_eigvecs(alpha, n, nev, lam, ptr<double>(h, L.stats), ptr<double>(h, L.U0),
                                  ptr<double>(h, L.U1), ptr<double>(h, L.U2), ptr<double>(h, L.Lm),
-                                 ptr<unsigned char>(h, L.Sw), ptr<double>(h, L.Yiv), Q, ldq, st);
+                                 ptr<unsigned char>(h, L.Sw), ptr<double>(h, L.Yiv), ptr<double>(h, L.ivfac), Q,
+                                 ldq, st);
     HCHK(hipGetLastError());
     int rc = orthogonalize(h, p, L, Q, ldq, n, nev);
     if (rc) return rc;

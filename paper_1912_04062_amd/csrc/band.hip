@@ -106,20 +106,30 @@ __global__ __launch_bounds__(256) void k_panel_qr(T *__restrict__ W, int ldw, in
         }
         ++nbar;
         if (!grid_sync_coh(bar, bar_base + nbar * G, err)) return;
-        if (tid < B) {
-            // batches of independent loads; the summation order (w ascending)
-            // is the same in every workgroup
+        {
+            // all threads: thread (tcol, tp) sums the partials of workgroups
+            // [tp*wc, (tp+1)*wc) with every load in flight at once, then the
+            // NP sums of a column are added in tp order; the order is the same
+            // in every workgroup (bitwise-identical scalars everywhere)
+            const int wc = (G + NP - 1) / NP;
+            const int wb = tp * wc, we = min(G, wb + wc);
             double s = 0.0;
-            for (int w0 = 0; w0 < G; w0 += 16) {
-                double t16[16];
+            for (int w0 = wb; w0 < we; w0 += 32) {
+                double t32[32];
 #pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    t16[q] = (w0 + q < G) ? ld_coh(&pbuf[((size_t)par * G + w0 + q) * B + tid]) : 0.0;
+                for (int q = 0; q < 32; ++q)
+                    t32[q] = (w0 + q < we) ? ld_coh(&pbuf[((size_t)par * G + w0 + q) * B + tcol]) : 0.0;
 #pragma unroll
-                for (int q = 0; q < 16; ++q) s += t16[q];
+                for (int q = 0; q < 32; ++q) s += t32[q];
             }
-            tot[tid] = s;
-            piv[tid] = ld_coh(&pvbuf[par * B + tid]);
+            if (tp == 0) piv[tcol] = ld_coh(&pvbuf[par * B + tcol]);
+            red[tid] = s;
+            __syncthreads();
+            if (tid < B) {
+                double a = 0.0;
+                for (int p = 0; p < NP; ++p) a += red[p * B + tid];
+                tot[tid] = a;
+            }
         }
         __syncthreads();
         // ---- T column l-1: T[0:l-1, l-1] = -tau_{l-1} T[0:l-1, 0:l-1] z

@@ -35,7 +35,7 @@ void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, do
                             double *w, hipStream_t st);
 void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
                             double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
-                            double *Q, int ldq, hipStream_t st);
+                            double *fac, double *Q, int ldq, hipStream_t st);
 void launch_chol_inv(const double *Gp, int nparts, int NB, double *Rinv, hipStream_t st);
 
 // backtransform.hip

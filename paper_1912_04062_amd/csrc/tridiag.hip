@@ -117,17 +117,27 @@ __device__ __forceinline__ double hash_uniform(unsigned long long seed, unsigned
     return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
 }
 
-// One thread per vector.  Workspace (each n x nev, [i][k] layout):
-// U0, U1, U2 (rows of U), Lm (multipliers, negative zero never used as flag:
-// swaps kept in Sw), Y (iterate).
-__global__ __launch_bounds__(256) void k_invit(const double *__restrict__ alpha, int n, int nev,
-                                               const double *__restrict__ w,
-                                               const double *__restrict__ stats, int iters,
-                                               double *__restrict__ U0, double *__restrict__ U1,
-                                               double *__restrict__ U2, double *__restrict__ Lm,
-                                               unsigned char *__restrict__ Sw, double *__restrict__ Y)
+// Inverse iteration, one thread per vector (one wavefront per workgroup so
+// that the vectors spread over as many CUs as possible).  Workspace (each
+// n x nev, [i][k] layout, so a wavefront's accesses are contiguous):
+// U0, U1, U2 (rows of U; U0 already clamped away from 0), Lm (multipliers),
+// Sw (row swaps), Y (iterate).  Every pass runs in chunks of IV_CH steps
+// whose loads are all issued before the chunk's sequential arithmetic.
+// The iterate is normalised on the fly (its norm is accumulated by the
+// previous backward pass), the start vector is generated, and the final
+// scaling (even and odd halves each to 1/sqrt(2) for lambda > 0) is left to
+// the transposition: fac[k] (even rows) and fac[nev + k] (odd rows).
+constexpr int IV_CH = 32;
+
+__global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, int n, int nev,
+                                              const double *__restrict__ w,
+                                              const double *__restrict__ stats, int iters,
+                                              double *__restrict__ U0, double *__restrict__ U1,
+                                              double *__restrict__ U2, double *__restrict__ Lm,
+                                              unsigned char *__restrict__ Sw, double *__restrict__ Y,
+                                              double *__restrict__ fac)
 {
-    const int k = blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.x * 64 + threadIdx.x;
     if (k >= nev) return;
     const size_t st = nev;
     const double g = stats[0];
@@ -141,71 +151,116 @@ __global__ __launch_bounds__(256) void k_invit(const double *__restrict__ alpha,
         while (k - r - 1 >= 0 && w[k - r - 1] == lam && r < 64) ++r;
         shift = lam + r * 10.0 * eps * fmax(fabs(lam), tiny);
     }
-    // factor T - shift I
-    double a = -shift, bb = (n > 1) ? alpha[0] : 0.0, cc = 0.0;
-    for (int i = 0; i + 1 < n; ++i) {
-        const double sub = alpha[i], dn = -shift, en = (i + 2 < n) ? alpha[i + 1] : 0.0;
-        if (fabs(a) >= fabs(sub)) {
-            if (a == 0.0) a = tiny;
-            const double l = sub / a;
-            Sw[i * st + k] = 0;
-            Lm[i * st + k] = l;
-            U0[i * st + k] = a; U1[i * st + k] = bb; U2[i * st + k] = cc;
-            a = dn - l * bb; bb = en - l * cc; cc = 0.0;
-        } else {
-            const double l = a / sub;
-            Sw[i * st + k] = 1;
-            Lm[i * st + k] = l;
-            U0[i * st + k] = sub; U1[i * st + k] = dn; U2[i * st + k] = en;
-            a = bb - l * dn; bb = cc - l * en; cc = 0.0;
+    auto clampu = [=](double u) { return (fabs(u) < tiny) ? ((u < 0.0) ? -tiny : tiny) : u; };
+    // factor T - shift I with partial pivoting (rows i, i+1 at step i)
+    {
+        double a = -shift, bb = (n > 1) ? alpha[0] : 0.0, cc = 0.0;
+        for (int i0 = 0; i0 + 1 < n; i0 += IV_CH) {
+            double al[IV_CH + 1];
+#pragma unroll
+            for (int j = 0; j <= IV_CH; ++j) {
+                const double x = alpha[min(i0 + j, n - 2)];
+                al[j] = (i0 + j < n - 1) ? x : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < IV_CH; ++j) {
+                const int i = i0 + j;
+                if (i + 1 >= n) continue;           // predicated (no break: keeps the loop unrolled)
+                const double sub = al[j], dn = -shift, en = al[j + 1];
+                if (fabs(a) >= fabs(sub)) {
+                    if (a == 0.0) a = tiny;
+                    const double l = sub / a;
+                    Sw[i * st + k] = 0;
+                    Lm[i * st + k] = l;
+                    U0[i * st + k] = clampu(a); U1[i * st + k] = bb; U2[i * st + k] = cc;
+                    a = dn - l * bb; bb = en - l * cc; cc = 0.0;
+                } else {
+                    const double l = a / sub;
+                    Sw[i * st + k] = 1;
+                    Lm[i * st + k] = l;
+                    U0[i * st + k] = clampu(sub); U1[i * st + k] = dn; U2[i * st + k] = en;
+                    a = bb - l * dn; bb = cc - l * en; cc = 0.0;
+                }
+            }
         }
+        if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
+        U0[(size_t)(n - 1) * st + k] = a;
     }
-    if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
-    U0[(size_t)(n - 1) * st + k] = a;
-#pragma unroll 8
-    for (int i = 0; i + 1 < n; ++i) {
-        double u = U0[i * st + k];
-        if (fabs(u) < tiny) U0[i * st + k] = (u < 0.0) ? -tiny : tiny;
-    }
-    // start vector
-#pragma unroll 8
-    for (int i = 0; i < n; ++i) Y[i * st + k] = hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i);
-    for (int it = 0; it < iters; ++it) {
+    // norm of the generated start vector
+    double inv;
+    {
         double s = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < n; ++i) { double yi = Y[i * st + k]; s += yi * yi; }
-        const double inv = 1.0 / sqrt(s);
-        // forward: P, L
-        double yprev = Y[k] * inv;
-#pragma unroll 8
-        for (int i = 0; i + 1 < n; ++i) {
-            double ynext = Y[(i + 1) * st + k] * inv;
-            double yi = yprev;
-            if (Sw[i * st + k]) { double tt = yi; yi = ynext; ynext = tt; }
-            ynext -= Lm[i * st + k] * yi;
-            Y[i * st + k] = yi;
-            yprev = ynext;
+        for (int i = 0; i < n; ++i) {
+            const double y = hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i);
+            s += y * y;
+        }
+        inv = 1.0 / sqrt(s);
+    }
+    double se = 0.0, so = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        // forward: P, L (row i+1 of the right-hand side enters at step i)
+        auto yin = [&](int i, double stored) -> double {
+            return (it == 0) ? hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i) * inv
+                             : stored * inv;
+        };
+        double yprev = yin(0, Y[k]);
+        for (int i0 = 0; i0 + 1 < n; i0 += IV_CH) {
+            double yv[IV_CH], lv[IV_CH];
+            unsigned char sv[IV_CH];
+#pragma unroll
+            for (int j = 0; j < IV_CH; ++j) {
+                // unconditional loads at a clamped row: all of the chunk's
+                // loads are in flight together (guards become selects)
+                const int ic = min(i0 + j, n - 2);
+                yv[j] = Y[(size_t)(ic + 1) * st + k];
+                lv[j] = Lm[(size_t)ic * st + k];
+                sv[j] = Sw[(size_t)ic * st + k];
+            }
+            __builtin_amdgcn_sched_barrier(0);     // keep the chunk's loads ahead of its arithmetic
+#pragma unroll
+            for (int j = 0; j < IV_CH; ++j) {
+                const int i = i0 + j;
+                if (i + 1 >= n) continue;
+                double ynext = yin(i + 1, yv[j]);
+                double yi = yprev;
+                if (sv[j]) { const double tt = yi; yi = ynext; ynext = tt; }
+                ynext -= lv[j] * yi;
+                Y[i * st + k] = yi;
+                yprev = ynext;
+            }
         }
         Y[(size_t)(n - 1) * st + k] = yprev;
-        // backward: U
+        // backward: U, accumulating the squared norms of the even and odd rows
         double x1 = 0.0, x2 = 0.0;
-#pragma unroll 8
-        for (int i = n - 1; i >= 0; --i) {
-            double r = Y[i * st + k];
-            if (i + 1 < n) r -= U1[i * st + k] * x1;
-            if (i + 2 < n) r -= U2[i * st + k] * x2;
-            double xi = r / U0[i * st + k];
-            Y[i * st + k] = xi;
-            x2 = x1;
-            x1 = xi;
+        se = 0.0;
+        so = 0.0;
+        for (int i1 = n - 1; i1 >= 0; i1 -= IV_CH) {
+            double rv[IV_CH], u0[IV_CH], u1[IV_CH], u2[IV_CH];
+#pragma unroll
+            for (int j = 0; j < IV_CH; ++j) {
+                const size_t ic = (size_t)max(i1 - j, 0);
+                rv[j] = Y[ic * st + k];
+                u0[j] = U0[ic * st + k];
+                u1[j] = U1[ic * st + k];
+                u2[j] = U2[ic * st + k];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < IV_CH; ++j) {
+                const int i = i1 - j;
+                if (i < 0) continue;
+                // U1, U2 of the last rows are never written: they multiply x1 = x2 = 0
+                const double xi = (rv[j] - ((i + 1 < n) ? u1[j] : 0.0) * x1 - ((i + 2 < n) ? u2[j] : 0.0) * x2) / u0[j];
+                Y[i * st + k] = xi;
+                if (i & 1) so += xi * xi;
+                else se += xi * xi;
+                x2 = x1;
+                x1 = xi;
+            }
         }
+        inv = 1.0 / sqrt(se + so);
     }
-    // normalise; for lambda > 0 the even and odd halves each to 1/sqrt(2)
-    double se = 0.0, so = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < n; i += 2) { double yi = Y[i * st + k]; se += yi * yi; }
-#pragma unroll 8
-    for (int i = 1; i < n; i += 2) { double yi = Y[i * st + k]; so += yi * yi; }
+    // final scaling factors
     double fe, fo;
     if (lam > 0.0 && se > 0.0 && so > 0.0) {
         fe = sqrt(0.5 / se);
@@ -213,14 +268,15 @@ __global__ __launch_bounds__(256) void k_invit(const double *__restrict__ alpha,
     } else {
         fe = fo = 1.0 / sqrt(se + so);
     }
-#pragma unroll 8
-    for (int i = 0; i < n; ++i) Y[i * st + k] *= (i & 1) ? fo : fe;
+    fac[k] = fe;
+    fac[nev + k] = fo;
 }
 
 // Odd n, lambda_0 = 0: q_0 = 1, q_{2m+2} = -alpha_{2m} q_{2m} / alpha_{2m+1},
 // odd entries 0; used only when every alpha_{2m+1} != 0 (else the inverse
 // iteration result stays).  Single thread; writes column 0 of Y ([i][k]).
-__global__ void k_nullvec(const double *__restrict__ alpha, int n, int nev, double *__restrict__ Y)
+__global__ void k_nullvec(const double *__restrict__ alpha, int n, int nev, double *__restrict__ Y,
+                          double *__restrict__ fac)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     for (int i = 1; i < n - 1; i += 2)
@@ -242,10 +298,14 @@ __global__ void k_nullvec(const double *__restrict__ alpha, int n, int nev, doub
     for (int i = 0; i < n; i += 2) ss += Y[i * st] * Y[i * st];
     const double inv = 1.0 / sqrt(ss);
     for (int i = 0; i < n; ++i) Y[i * st] = (i & 1) ? 0.0 : Y[i * st] * inv;
+    fac[0] = 1.0;
+    fac[nev] = 1.0;
 }
 
-// Y ([i][k], n x nev) -> Q (column-major, ldq)
-__global__ void k_transpose(const double *__restrict__ Y, int n, int nev, double *__restrict__ Q, int ldq)
+// Y ([i][k], n x nev) -> Q (column-major, ldq), row i of column k scaled by
+// fac[k] (even i) or fac[nev + k] (odd i)
+__global__ void k_transpose(const double *__restrict__ Y, int n, int nev, const double *__restrict__ fac,
+                            double *__restrict__ Q, int ldq)
 {
     __shared__ double tile[32][33];
     const int k0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
@@ -257,7 +317,7 @@ __global__ void k_transpose(const double *__restrict__ Y, int n, int nev, double
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         int k = k0 + r, i = i0 + tx;
-        if (i < n && k < nev) Q[(size_t)k * ldq + i] = tile[tx][r];
+        if (i < n && k < nev) Q[(size_t)k * ldq + i] = tile[tx][r] * fac[(i & 1) ? nev + k : k];
     }
 }
 
@@ -341,14 +401,14 @@ void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, do
 
 void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
                             double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
-                            double *Q, int ldq, hipStream_t st)
+                            double *fac, double *Q, int ldq, hipStream_t st)
 {
     if (nev <= 0) return;
-    hipLaunchKernelGGL(k_invit, dim3(cdiv(nev, 256)), dim3(256), 0, st, alpha, n, nev, w, stats, 3, U0, U1, U2,
-                       Lm, Sw, Y);
-    if (n & 1) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, alpha, n, nev, Y);
+    hipLaunchKernelGGL(k_invit, dim3(cdiv(nev, 64)), dim3(64), 0, st, alpha, n, nev, w, stats, 3, U0, U1, U2,
+                       Lm, Sw, Y, fac);
+    if (n & 1) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, alpha, n, nev, Y, fac);
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(nev, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Y, n,
-                       nev, Q, ldq);
+                       nev, (const double *)fac, Q, ldq);
 }
 
 void launch_chol_inv(const double *Gp, int nparts, int NB, double *Rinv, hipStream_t st)
