@@ -26,6 +26,32 @@ PEAK = {"f64": 78.6, "f32": 157.3}          # TFLOP/s, dense MFMA/vector
 HBM_PEAK = 8000.0                           # GB/s
 
 
+def traffic_record(stage):
+    """HBM bytes per launch of the kernel behind `stage`, from a committed
+    counter profile (profiles/traffic_*.md: FETCH_SIZE and WRITE_SIZE passes
+    scaled by a plain copy of known size), or None when there is none or when
+    the kernel's source region has changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-record: "):
+                    continue
+                rec = json.loads(line[len("traffic-record: "):])
+                if rec.get("stage") != stage:
+                    continue
+                with open(os.path.join(ROOT, rec["source"])) as g:
+                    src = g.read()
+                i, j = src.find(rec["region_begin"]), src.find(rec["region_end"])
+                if i < 0 or j < i:
+                    return None
+                if hashlib.sha256(src[i:j].encode()).hexdigest() != rec["region_sha256"]:
+                    return None
+                return rec["traffic_bytes"]
+    return None
+
+
 def useful_flops(n, nev):
     return 4.0 / 3.0 * n ** 3 + 8.0 * n * n * nev
 
@@ -146,8 +172,12 @@ def main():
         achieved = kinfo["flops"] / (kern[dom] * 1e-3) / 1e12
         roof = {"bound": kinfo["bound"], "achieved": achieved, "peak": PEAK[kdtype], "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = traffic_record(dom) if best == "fp64" else None
     roof["kernel"] = dom
+    roof["gpu_kernel"] = {"panel_qr": "k_panel_qr", "bulge_chase": "k_bulge_chase", "bt2": "k_bt2_win",
+                          "bt1": "k_bt1_w + k_bt1_t + k_bt1_z", "tridiag": "k_bisect + k_invit + orthogonalization",
+                          "skew_symm_w": "k_skew_symm + k_gram + k_small + k_wform",
+                          "skew_syr2k": "k_skew_syr2k", "refine": "refinement kernels"}.get(dom, dom)
     roof["launches_per_step"] = kinfo["launches"]
     roof["ms_per_step"] = kern[dom]
     roof["kernels_ms"] = kern

@@ -69,7 +69,7 @@ typedef struct skew_evd_opts {
 #define SKEW_EVD_K_SYR2K 2   /* A += V W^T - W V^T (full-to-band) */
 #define SKEW_EVD_K_CHASE 3   /* bulge chasing */
 #define SKEW_EVD_K_TRIDIAG 4 /* bisection, inverse iteration, Gram-Schmidt */
-#define SKEW_EVD_K_BT2 5     /* stage-2 back-transformation (incl. D and T factors) */
+#define SKEW_EVD_K_BT2 5     /* stage-2 back-transformation (the application kernel) */
 #define SKEW_EVD_K_BT1 6     /* stage-1 back-transformation */
 #define SKEW_EVD_K_REFINE 7  /* refinement (precision form) */
 #define SKEW_EVD_NKERN 8

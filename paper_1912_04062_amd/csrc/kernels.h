@@ -39,11 +39,13 @@ void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w
 void launch_chol_inv(const double *Gp, int nparts, int NB, double *Rinv, hipStream_t st);
 
 // backtransform.hip
+// launch_bt2 phases: bit 0 = T factors of the reflector groups, bit 1 = application.
 template <typename T>
 void launch_dscale(const double *Q, int ldq, int n, int nev, T *Z, int ldz, hipStream_t st);
 template <typename T>
 void launch_bt2(T *Z, int ldz, int n, int ncols, int b, int nb2, const double *V2, const double *tau2, T *T2,
-                T *V2t, const int *goff_dev, int nsig, int ngroups, hipStream_t st);
+                T *V2t, const int *goff_dev, int nsig, int ngroups, int phases,
+                hipStream_t st);
 int tn_splits(int K, int tiles);
 template <typename T>
 int launch_gemm_tn_part(const T *A, int lda, const T *B, int ldb, int M, int N, int K, double *Cpart,
