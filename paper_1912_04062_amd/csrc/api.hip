@@ -70,7 +70,7 @@ namespace {
 // Workspace layout.  Offsets are 256-byte aligned.
 struct Layout {
     size_t W, Vall, Tall, tauall, Ypart, Y0, Wd, Gp, Tx, part, ab, goff, V2, tau2, T2, V2t, alpha, a2, stats,
-        lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, Qd, Z, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
+        lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, Qd, Z, cq, cqGp, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
         rstat, Tm, total;
     std::vector<size_t> Voff;
 };
@@ -78,6 +78,15 @@ struct Layout {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int tn_parts_max() { return 32; }
+
+// Row splits of the Gram products of the Cholesky-QR panel path: about 256
+// rows per workgroup, at most cholqr_max_splits().
+int cholqr_max_splits() { return 64; }
+int cholqr_splits(int m)
+{
+    int S = (m + 255) / 256;
+    return S < 1 ? 1 : (S > cholqr_max_splits() ? cholqr_max_splits() : S);
+}
 
 Layout plan_layout(const Plan &p)
 {
@@ -128,6 +137,8 @@ Layout plan_layout(const Plan &p)
     L.ivfac = take(sizeof(double) * 2 * nev);
     L.Qd = take(sizeof(double) * n * nev);
     L.Z = take(es * n * 2 * nev);
+    L.cq = take(sizeof(double) * skew::cholqr_scratch_doubles());
+    L.cqGp = take(sizeof(double) * (size_t)cholqr_max_splits() * b * b);
     L.Wp = take(sizeof(double) * tn_parts_max() * b * 2 * nev);
     L.Wt2 = take(sizeof(double) * 2 * b * 2 * nev);
     const size_t wmax = std::max((size_t)p.orth_window, (size_t)ORTH_NB);
@@ -156,7 +167,7 @@ Layout plan_layout(const Plan &p)
 }
 
 // control words
-enum { CTL_FLAGS = 0, CTL_ERR = 1, CTL_BAR = 2, CTL_PROGRESS = 64 };
+enum { CTL_FLAGS = 0, CTL_ERR = 1, CTL_BAR = 2, CTL_QRFLAG = 3, CTL_PROGRESS = 64 };
 
 int auto_band(int n)
 {
@@ -306,9 +317,32 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
         const int c0 = j * b, r0 = c0 + b, m = n - r0;
         T *Vd = ptr<T>(h, L.Vall) + L.Voff[j];
         double *Tf = ptr<double>(h, L.Tall) + (size_t)j * b * b;
+        double *tauj = ptr<double>(h, L.tauall) + (size_t)j * b;
         HCHK(kt_begin(h, SKEW_EVD_K_PANEL));
-        HCHK(skew::launch_panel_qr<T>(W, n, c0, r0, m, b, Vd, ptr<double>(h, L.tauall) + (size_t)j * b, Tf,
-                                      ptr<double>(h, L.part), ctl + CTL_BAR, bar_base, ctl + CTL_ERR, st));
+        const unsigned *skip = nullptr;
+        if (sizeof(T) == sizeof(double) && m >= b) {
+            // Cholesky QR twice + Householder reconstruction; the Householder
+            // panel kernel below runs only when this path flags the panel
+            double *P = (double *)(void *)W + (size_t)c0 * n + r0;
+            double *Vq = (double *)(void *)Vd;
+            double *cq = ptr<double>(h, L.cq), *Gq = ptr<double>(h, L.cqGp);
+            unsigned *qf = ctl + CTL_QRFLAG;
+            const size_t BB = (size_t)64 * 64;
+            int S = skew::launch_gemm_tn_part<double>(P, n, P, n, b, b, m, Gq, st, cholqr_splits(m));
+            skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
+            skew::launch_chol_qr(b, 1, cq, qf, st);
+            skew::launch_gemm_nn<double>(P, n, cq + skew::CQ_R1INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
+            S = skew::launch_gemm_tn_part<double>(Vq, m, Vq, m, b, b, m, Gq, st, cholqr_splits(m));
+            skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
+            skew::launch_chol_qr(b, 2, cq, qf, st);
+            skew::launch_gemm_nn<double>(Vq, m, cq + skew::CQ_R2INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
+            skew::launch_hh_rebuild(Vq, m, b, P, n, cq, Tf, tauj, qf, st);
+            if (m > b)
+                skew::launch_gemm_nn<double>(Vq + b, m, cq + skew::CQ_UINV * BB, 1, m - b, b, b, Vq + b, m, 1.0, 0, st);
+            skip = qf;
+        }
+        HCHK(skew::launch_panel_qr<T>(W, n, c0, r0, m, b, Vd, tauj, Tf, ptr<double>(h, L.part), ctl + CTL_BAR,
+                                      bar_base, ctl + CTL_ERR, skip, st));
         HCHK(kt_end(h, SKEW_EVD_K_PANEL));
         bar_base += (unsigned)((std::min(m, b) + 1) * skew::panel_qr_groups(m));
         if (m > 1) {

@@ -42,7 +42,8 @@ __global__ void k_dscale(const double *__restrict__ Q, int ldq, int n, int nev, 
 // One workgroup per group; nb2 <= 64, b <= 64.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bt2_tfac(const double *__restrict__ V2, const double *__restrict__ tau2,
-                                                  int b, int nb2, T *__restrict__ T2, T *__restrict__ V2t)
+                                                  int b, int nb2, T *__restrict__ T2, T *__restrict__ V2t,
+                                                  int rowmajor)
 {
     __shared__ double Vs[64 * 65];       // Vs[r][i]
     __shared__ double Gm[64 * 65];       // Gram (upper)
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) void k_bt2_tfac(const double *__restrict__ V2,
     T *To = T2 + g * (size_t)nb2 * nb2;
     for (int e = tid; e < nb2 * nb2; e += 256) {
         int i = e % nb2, j = e / nb2;
-        To[e] = (T)Tm[i * 65 + j];       // column-major
+        To[e] = rowmajor ? (T)Tm[j * 65 + i] : (T)Tm[i * 65 + j];   // row- or column-major
     }
 }
 
@@ -285,8 +286,17 @@ __device__ __forceinline__ size_t gid(const Cur &c, const int *goff)
     return (c.w == 0) ? (size_t)goff[c.sh] + c.tau : (size_t)goff[c.sh - 1] + c.tau - 1;
 }
 
-// V then T of group g (32 KB each) into Vl / Tl: wave w moves 1 KB chunks
-// 16w .. 16w + 15 (chunks 0..31 are V, 32..63 are T), 16 bytes per lane.
+// LDS image of a group: V (b x nb2 column-major) and T (row-major), each
+// moved as 32 chunks of 1 KB (two columns of V, two rows of T) that are
+// padded apart (PV, PT doubles) so that the MFMA operand reads spread over
+// the banks.  V[d][i] is at chunk i/2, offset 64 (i%2) + d; T[i][u] at chunk
+// i/2, offset 64 (i%2) + u.
+constexpr int PV = 6, PT = 4;
+constexpr int CV = 128 + PV, CT = 128 + PT;     // chunk strides
+constexpr int BUF = 32 * CV + 32 * CT;          // one buffer (V then T)
+
+// V then T of group g into Vl / Tl: wave w moves chunks 16w .. 16w + 15
+// (0..31 of V, then 0..31 of T), 16 bytes per lane.
 __device__ __forceinline__ void prefetch(const double *__restrict__ V2, const double *__restrict__ T2, size_t g,
                                          double *Vl, double *Tl)
 {
@@ -294,11 +304,12 @@ __device__ __forceinline__ void prefetch(const double *__restrict__ V2, const do
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double *src = (wv < 2) ? V2 + g * (B * B) : T2 + g * (B * B);
     double *dst = (wv < 2) ? Vl : Tl;
+    const int cs = (wv < 2) ? CV : CT;
     const int c0 = (wv & 1) * 16;
 #pragma unroll
     for (int j = 0; j < 16; ++j)
         __builtin_amdgcn_global_load_lds((gbl_void *)(src + (size_t)(c0 + j) * 128 + 2 * lane),
-                                         (lds_void *)(dst + (c0 + j) * 128), 16, 0, 0);
+                                         (lds_void *)(dst + (c0 + j) * cs), 16, 0, 0);
 }
 
 __device__ __forceinline__ bool blk_ok(int x, int n) { return x >= 0 && 1 + 64 * x < n; }
@@ -354,9 +365,8 @@ __device__ __forceinline__ void store_block(const d4 (&zb)[4], double *__restric
 }
 
 // Z[slots S0, S1] <- (I - Vp T Vp^T) Z[slots S0, S1]; Vp is the 128 x 64
-// parallelogram Vp[r][i] = V[r - i][i] (0 <= r - i < 64), V compact in Vl
-// (V[d][i] at 64 i + d, with VPAD readable elements on both sides), T compact
-// in Tl (T[i][u] at 64 u + i).
+// parallelogram Vp[r][i] = V[r - i][i] (0 <= r - i < 64), V and T in the
+// padded LDS image above.
 //
 // Every LDS operand address is a per-lane base plus a compile-time offset,
 // and the parallelogram test is a compare of a per-lane constant with a
@@ -365,17 +375,15 @@ __device__ __forceinline__ void store_block(const d4 (&zb)[4], double *__restric
 // alive across the group loop.  Each phase runs its k-steps outermost so that
 // MFMAs of independent output tiles follow each other, and loads the LDS
 // operands of a chunk of k-steps before the chunk's MFMAs.
-constexpr int VPAD = 96;
-
 template <int S0, int S1>
 __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl)
 {
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));
     const int lr = lane & 15, lk = lane >> 4;
-    // W1 = Vp^T Zg: element (i = 16mt + lr, r = 4ks + lk) at 63 lr + lk + (1008 mt + 4 ks),
-    // inside the parallelogram when 0 <= lk - lr + 4ks - 16mt < 64
-    const double *vb1 = Vl + 63 * lr + lk;
+    // W1 = Vp^T Zg: element (i = 16mt + lr, r = 4ks + lk) at chunk 8mt + lr/2, offset
+    // 64 (lr % 2) + lk - lr + 4ks - 16mt; inside when 0 <= lk - lr + 4ks - 16mt < 64
+    const double *vb1 = Vl + (lr >> 1) * CV + (lr & 1) * 64 + lk - lr;
     const int dw = lk - lr;
     d4 w1[4];
 #pragma unroll
@@ -389,7 +397,7 @@ __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl
             for (int mt = 0; mt < 4; ++mt) {
                 const int ks = kc + kk;
                 if (ks >= 4 * mt && ks < 4 * mt + 20) {
-                    const double x = vb1[1008 * mt + 4 * ks];
+                    const double x = vb1[8 * mt * CV + 4 * ks - 16 * mt];
                     const int d = dw + 4 * ks - 16 * mt;
                     a[kk][mt] = ((unsigned)d < (unsigned)B) ? x : 0.0;
                 } else {
@@ -405,8 +413,9 @@ __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl
                 if (ks >= 4 * mt && ks < 4 * mt + 20) w1[mt] = mfma_16x16x4(a[kk][mt], bz, w1[mt]);
         }
     }
-    // W2 = T W1 (T upper triangular): T[16mt + lr][4ks + lk] at 64 lk + lr + (256 ks + 16 mt)
-    const double *tb = Tl + 64 * lk + lr;
+    // W2 = T W1 (T upper triangular): T[16mt + lr][4ks + lk] at chunk 8mt + lr/2,
+    // offset 64 (lr % 2) + lk + 4ks
+    const double *tb = Tl + (lr >> 1) * CT + (lr & 1) * 64 + lk;
     d4 w2[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) w2[mt] = (d4){0.0, 0.0, 0.0, 0.0};
@@ -418,7 +427,7 @@ __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const int ks = kc + kk;
-                a[kk][mt] = (ks >= 4 * mt) ? tb[256 * ks + 16 * mt] : 0.0;
+                a[kk][mt] = (ks >= 4 * mt) ? tb[8 * mt * CT + 4 * ks] : 0.0;
             }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -428,9 +437,9 @@ __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl
                 if (ks >= 4 * mt) w2[mt] = mfma_16x16x4(a[kk][mt], w1[ks >> 2][ks & 3], w2[mt]);
         }
     }
-    // Zg -= Vp W2: element (r = 16rt + lr, i = 4ks + lk) at 63 lk + lr + (252 ks + 16 rt),
-    // inside when 0 <= lr - lk + 16rt - 4ks < 64
-    const double *vb3 = Vl + 63 * lk + lr;
+    // Zg -= Vp W2: element (r = 16rt + lr, i = 4ks + lk) at chunk 2ks + lk/2, offset
+    // 64 (lk % 2) + lr - lk + 16rt - 4ks; inside when 0 <= lr - lk + 16rt - 4ks < 64
+    const double *vb3 = Vl + (lk >> 1) * CV + (lk & 1) * 64 + lr - lk;
     const int dz = lr - lk;
 #pragma unroll
     for (int kc = 0; kc < 16; kc += 2) {
@@ -441,7 +450,7 @@ __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl
             for (int rt = 0; rt < 8; ++rt) {
                 const int ks = kc + kk, i4 = 4 * ks;
                 if (!(i4 + 3 < 16 * rt - B + 1 || i4 >= 16 * rt + 16)) {
-                    const double x = vb3[252 * ks + 16 * rt];
+                    const double x = vb3[2 * ks * CV + 16 * rt - 4 * ks];
                     const int d = dz + 16 * rt - 4 * ks;
                     a[kk][rt] = ((unsigned)d < (unsigned)B) ? -x : 0.0;
                 } else {
@@ -470,10 +479,9 @@ __global__ __launch_bounds__(256) void k_bt2_win(double *__restrict__ Z, int ldz
 {
     using namespace bt2p;
     extern __shared__ double lds[];
-    // buffer q: V (with VPAD readable doubles before and after), then T
-    constexpr int BUF = VPAD + B * B + VPAD + B * B;
-    auto Vl = [&](int q) -> double * { return lds + q * BUF + VPAD; };
-    auto Tl = [&](int q) -> double * { return lds + q * BUF + VPAD + B * B + VPAD; };
+    // buffer q: V image, then T image
+    auto Vl = [&](int q) -> double * { return lds + q * BUF; };
+    auto Tl = [&](int q) -> double * { return lds + q * BUF + 32 * CV; };
     const int col0 = blockIdx.x * 64;
     const int ncl = min(64, ncols - col0);
     if (nsig <= 0) return;
@@ -806,11 +814,13 @@ void launch_bt2(T *Z, int ldz, int n, int ncols, int b, int nb2, const double *V
                 T *V2t, const int *goff_dev, int nsig, int ngroups, int phases, hipStream_t st)
 {
     if (ngroups <= 0 || ncols <= 0) return;
-    if (phases & 1) hipLaunchKernelGGL(k_bt2_tfac<T>, dim3(ngroups), dim3(256), 0, st, V2, tau2, b, nb2, T2, V2t);
+    const bool win = sizeof(T) == sizeof(double) && b == 64 && nb2 == 64;   // window kernel: T row-major
+    if (phases & 1)
+        hipLaunchKernelGGL(k_bt2_tfac<T>, dim3(ngroups), dim3(256), 0, st, V2, tau2, b, nb2, T2, V2t, win ? 1 : 0);
     if (!(phases & 2)) return;
     const T *Vuse = V2t ? (const T *)V2t : (const T *)(const void *)V2;
-    if (sizeof(T) == sizeof(double) && b == 64 && nb2 == 64) {
-        const size_t shm = sizeof(double) * 2 * (2 * bt2p::VPAD + 2 * 64 * 64);
+    if (win) {
+        const size_t shm = sizeof(double) * 2 * bt2p::BUF;
         static bool attr = false;
         if (!attr) {
             (void)hipFuncSetAttribute((const void *)k_bt2_win, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -835,12 +845,13 @@ int tn_splits(int K, int tiles)
 }
 
 template <typename T>
-int launch_gemm_tn_part(const T *A, int lda, const T *B, int ldb, int M, int N, int K, double *Cpart, hipStream_t st)
+int launch_gemm_tn_part(const T *A, int lda, const T *B, int ldb, int M, int N, int K, double *Cpart, hipStream_t st,
+                        int S_req)
 {
     // returns the number of partial products written
     const int TM = 64, TN = 64;
     unsigned tiles = cdiv(M, TM) * cdiv(N, TN);
-    int S = tn_splits(K, (int)tiles);
+    int S = S_req > 0 ? S_req : tn_splits(K, (int)tiles);
     int kc = (int)(cdiv(cdiv(K, S), 16) * 16);
     S = (int)cdiv(K, kc);
     dim3 grid(cdiv(M, TM), cdiv(N, TN), S);
@@ -950,9 +961,9 @@ template void launch_bt2<double>(double *, int, int, int, int, int, const double
 template void launch_bt2<float>(float *, int, int, int, int, int, const double *, const double *, float *, float *,
                                 const int *, int, int, int, hipStream_t);
 template int launch_gemm_tn_part<double>(const double *, int, const double *, int, int, int, int, double *,
-                                         hipStream_t);
+                                         hipStream_t, int);
 template int launch_gemm_tn_part<float>(const float *, int, const float *, int, int, int, int, double *,
-                                        hipStream_t);
+                                        hipStream_t, int);
 template void launch_gemm_nn<double>(const double *, int, const double *, int, int, int, int, double *, int, double,
                                      int, hipStream_t);
 template void launch_gemm_nn<float>(const float *, int, const double *, int, int, int, int, float *, int, double,

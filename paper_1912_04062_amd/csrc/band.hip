@@ -58,7 +58,8 @@ template <typename T, int B>
 __global__ __launch_bounds__(256) void k_panel_qr(T *__restrict__ W, int ldw, int c0, int r0, int m,
                                                   T *__restrict__ Vd, double *__restrict__ tau,
                                                   double *__restrict__ Tf, double *__restrict__ part,
-                                                  unsigned *bar, unsigned bar_base, unsigned *err)
+                                                  unsigned *bar, unsigned bar_base, unsigned *err,
+                                                  const unsigned *__restrict__ skip)
 {
     extern __shared__ double sm[];
     double *P = sm;                        // [ROWS][B]
@@ -74,6 +75,12 @@ __global__ __launch_bounds__(256) void k_panel_qr(T *__restrict__ W, int ldw, in
     const int L = m < B ? m : B;           // columns that get a reflector
     double *pbuf = part;                   // [2][G][B]
     double *pvbuf = part + 2 * (size_t)G * B;  // [2][B]
+    if (skip && *skip == 0u) {
+        // the Cholesky-QR path factored this panel: advance the barrier
+        // counter as the L + 1 barriers of this launch would have
+        if (tid == 0) __hip_atomic_fetch_add(bar, (unsigned)(L + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
 
     for (int e = tid; e < PQR_ROWS * B; e += 256) {
         int g = e / B, t = e % B;
@@ -383,6 +390,235 @@ __global__ void k_band_extract(const T *__restrict__ W, int ldw, int n, int b,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Panel factorization by Cholesky QR twice plus Householder reconstruction
+// (FP64, panel P of m >= B rows, B <= 64):
+//   G1 = P^T P = R1^T R1,  Q1 = P R1^{-1},  G2 = Q1^T Q1 = R2^T R2,
+//   Q = Q1 R2^{-1},  R = R2 R1,
+// then the compact-WY form of the same orthogonal factor: the LU
+// factorization Q[0:B, :] - S = L U with the signs S = diag(s_i) chosen on the
+// fly (s_i = -sign of the pivot, so that |u_ii| >= 1 and no pivoting is
+// needed) gives V = [L; Q[B:, :] U^{-1}], T = -U S L^{-T} and R_h = S R, with
+// (I - V T V^T)^T P = [R_h; 0].  A Cholesky pivot that signals a panel too
+// ill-conditioned (or rank deficient) for two passes sets the flag, and the
+// Householder panel kernel takes over.
+//
+// Small 64 x 64 kernels: thread (tx, ty) = (tid % 64, tid / 64) owns row tx
+// and columns ty + 4q (q = 0..15).
+// Scratch layout (cq, doubles): G, R1, R1inv, R2inv, R, Uinv (indices CQ_*),
+// each 64 x 64 column-major.
+using skew::CQ_G;
+using skew::CQ_R1;
+using skew::CQ_R1INV;
+using skew::CQ_R2INV;
+using skew::CQ_R;
+using skew::CQ_UINV;
+
+// G[e] = sum over np partials (each B*B, column-major), in order.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ Gp, int np, int BB,
+                                                     double *__restrict__ G)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= BB) return;
+    double s = 0.0;
+    for (int p0 = 0; p0 < np; p0 += 16) {
+        double t[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int p = min(p0 + q, np - 1);
+            t[q] = Gp[(size_t)p * BB + e];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (p0 + q < np) s += t[q];
+    }
+    G[e] = s;
+}
+
+// Cholesky factor R (upper, G = R^T R) and R^{-1} of the Gram matrix in
+// cq[CQ_G].  pass 1: R1, R1^{-1}; flag = 1 when a pivot falls below
+// 1e-13 max_i G_ii (condition of the panel beyond what two passes restore).
+// pass 2 (skipped when the flag is set): R2^{-1} and R = R2 R1; flag = 1 when
+// a pivot of G2 (close to I) leaves [0.5, 2].
+__global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__restrict__ cq,
+                                                 unsigned *__restrict__ flag)
+{
+    __shared__ double M[64 * 65], X[64 * 65], part[4][64];
+    __shared__ int bad;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    if (pass == 2 && *flag) return;
+    const size_t BB = 64 * 64;
+    const double *G = cq + CQ_G * BB;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int j = ty + 4 * q;
+        M[tx * 65 + j] = (tx < B && j < B) ? G[(size_t)j * B + tx] : 0.0;
+        X[tx * 65 + j] = 0.0;
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    double dmax = 0.0;
+    for (int i = 0; i < B; ++i) dmax = fmax(dmax, M[i * 65 + i]);
+    const double lo = (pass == 1) ? 1e-13 * dmax : 0.5, hi = (pass == 1) ? 2.0 * dmax : 2.0;
+    // G = R^T R, R upper in the upper triangle of M, right-looking
+    for (int j = 0; j < B; ++j) {
+        const double d = M[j * 65 + j];
+        if (!(d > lo && d < hi)) {                 // uniform: every thread reads the same d
+            if (tid == 0) bad = 1;
+            break;
+        }
+        const double rjj = sqrt(d), ir = 1.0 / rjj;
+        const double rjr = (tx > j && tx < B) ? M[j * 65 + tx] * ir : 0.0;
+        double rjc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = ty + 4 * q;
+            rjc[q] = (c > j && c < B) ? M[j * 65 + c] * ir : 0.0;
+        }
+        __syncthreads();
+        if (ty == 0) {
+            if (tx == j) M[j * 65 + j] = rjj;
+            else if (tx > j && tx < B) M[j * 65 + tx] = rjr;
+        }
+        if (tx > j && tx < B) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int c = ty + 4 * q;
+                if (c >= tx && c < B) M[tx * 65 + c] -= rjr * rjc[q];
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) *flag = 1u;
+        return;
+    }
+    // R^{-1} by rows from the bottom; column c = tx, the sum over u split over the four waves
+    for (int i = B - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int u = i + 1 + ty; u <= tx && u < B; u += 4) s += M[i * 65 + u] * X[u * 65 + tx];
+        part[ty][tx] = s;
+        __syncthreads();
+        if (ty == 0 && tx < B && i <= tx)
+            X[i * 65 + tx] = (((i == tx) ? 1.0 : 0.0) - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx])) /
+                             M[i * 65 + i];
+        __syncthreads();
+    }
+    double *Ro = cq + ((pass == 1) ? CQ_R1 : CQ_R) * BB;
+    double *Ri = cq + ((pass == 1) ? CQ_R1INV : CQ_R2INV) * BB;
+    const double *R1 = cq + CQ_R1 * BB;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int j = ty + 4 * q;
+        if (tx < B && j < B) {
+            Ri[(size_t)j * B + tx] = (tx <= j) ? X[tx * 65 + j] : 0.0;
+            double r;
+            if (pass == 1) {
+                r = (tx <= j) ? M[tx * 65 + j] : 0.0;
+            } else {                               // (R2 R1)[tx][j] = sum_{tx <= u <= j} R2[tx][u] R1[u][j]
+                r = 0.0;
+                for (int u = tx; u <= j; ++u) r += M[tx * 65 + u] * R1[(size_t)j * B + u];
+            }
+            Ro[(size_t)j * B + tx] = r;
+        }
+    }
+    if (pass == 1 && tid == 0) *flag = 0u;
+}
+
+// Householder reconstruction from the orthonormal Q (in Vd, m x B, ld m):
+// writes V's top block L into Vd, T into Tf (column-major), tau = diag(T),
+// R_h = S R into the panel's top block of W (upper triangle), U^{-1} into
+// cq[CQ_UINV].  Nothing is done when the flag is set.
+__global__ __launch_bounds__(256) void k_hh_rebuild(double *__restrict__ Vd, int m, int B, double *__restrict__ Wp,
+                                                    int ldw, double *__restrict__ cq, double *__restrict__ Tf,
+                                                    double *__restrict__ tau, const unsigned *__restrict__ flag)
+{
+    __shared__ double M[64 * 65], X[64 * 65], Y[64 * 65], sgn[64], part[4][64];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    if (*flag) return;
+    const size_t BB = 64 * 64;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int j = ty + 4 * q;
+        M[tx * 65 + j] = (tx < B && j < B) ? Vd[(size_t)j * m + tx] : 0.0;
+    }
+    __syncthreads();
+    // LU of Q_top - S without pivoting: L unit lower (below the diagonal of
+    // M), U upper (on and above it)
+    for (int i = 0; i < B; ++i) {
+        const double p0 = M[i * 65 + i];
+        const double si = (p0 >= 0.0) ? -1.0 : 1.0;
+        const double piv = p0 - si, ip = 1.0 / piv;
+        const double lr = (tx > i && tx < B) ? M[tx * 65 + i] * ip : 0.0;
+        double ur[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = ty + 4 * q;
+            ur[q] = (c > i && c < B) ? M[i * 65 + c] : 0.0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            M[i * 65 + i] = piv;
+            sgn[i] = si;
+        }
+        if (ty == 0 && tx > i && tx < B) M[tx * 65 + i] = lr;
+        if (tx > i && tx < B) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int c = ty + 4 * q;
+                if (c > i && c < B) M[tx * 65 + c] -= lr * ur[q];
+            }
+        }
+        __syncthreads();
+    }
+    // X = U^{-1} (rows from the bottom; column tx, the sum over u split over
+    // the four waves), Y = L^{-1} (rows from the top)
+    for (int i = B - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int u = i + 1 + ty; u <= tx && u < B; u += 4) s += M[i * 65 + u] * X[u * 65 + tx];
+        part[ty][tx] = s;
+        __syncthreads();
+        if (ty == 0 && tx < B)
+            X[i * 65 + tx] = (i <= tx) ? (((i == tx) ? 1.0 : 0.0) - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx])) /
+                                             M[i * 65 + i]
+                                       : 0.0;
+        __syncthreads();
+    }
+    for (int i = 0; i < B; ++i) {
+        double s = 0.0;
+        if (ty == 0 && tx < B) {
+            for (int u = 0; u < i; ++u) s += M[i * 65 + u] * Y[u * 65 + tx];
+            Y[i * 65 + tx] = (i == tx) ? 1.0 : ((i > tx) ? -s : 0.0);
+        }
+        __syncthreads();
+    }
+    // T = -U S L^{-T}:  T[r][c] = -sum_{r <= k <= c} U[r][k] s_k Linv[c][k]
+    double *Tout = Tf;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int c = ty + 4 * q, r = tx;
+        if (r < B && c < B) {
+            double t = 0.0;
+            for (int k = r; k <= c; ++k) t += M[r * 65 + k] * sgn[k] * Y[c * 65 + k];
+            Tout[(size_t)c * B + r] = (r <= c) ? -t : 0.0;
+            if (r == c) tau[r] = -t;
+        }
+    }
+    // V top block (unit lower), U^{-1}, R_h = S R (upper triangle of the top block)
+    const double *R = cq + CQ_R * BB;
+    double *Ui = cq + CQ_UINV * BB;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int c = ty + 4 * q, r = tx;
+        if (r < B && c < B) {
+            Vd[(size_t)c * m + r] = (r > c) ? M[r * 65 + c] : ((r == c) ? 1.0 : 0.0);
+            Ui[(size_t)c * B + r] = (r <= c) ? X[r * 65 + c] : 0.0;
+            if (r <= c) Wp[(size_t)c * ldw + r] = sgn[r] * R[(size_t)c * B + r];
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -403,7 +639,7 @@ size_t panel_qr_part_doubles(int m, int B) { return 2 * (size_t)panel_qr_groups(
 template <typename T, int B>
 static hipError_t panel_qr_b(T *W, int ldw, int c0, int r0, int m, T *Vd, double *tau, double *Tf,
                              double *part, unsigned *bar, unsigned bar_base, unsigned *err,
-                             hipStream_t st)
+                             const unsigned *skip, hipStream_t st)
 {
     const int G = panel_qr_groups(m);
     size_t shm = sizeof(double) * ((size_t)PQR_ROWS * B + (size_t)B * B);
@@ -413,19 +649,20 @@ static hipError_t panel_qr_b(T *W, int ldw, int c0, int r0, int m, T *Vd, double
                             (int)shm);
         attr = true;
     }
-    void *args[] = {&W, &ldw, &c0, &r0, &m, &Vd, &tau, &Tf, &part, &bar, &bar_base, &err};
+    void *args[] = {&W, &ldw, &c0, &r0, &m, &Vd, &tau, &Tf, &part, &bar, &bar_base, &err, &skip};
     return hipLaunchCooperativeKernel((const void *)k_panel_qr<T, B>, dim3(G), dim3(256), args, shm, st);
 }
 
 template <typename T>
 hipError_t launch_panel_qr(T *W, int ldw, int c0, int r0, int m, int B, T *Vd, double *tau, double *Tf,
-                           double *part, unsigned *bar, unsigned bar_base, unsigned *err, hipStream_t st)
+                           double *part, unsigned *bar, unsigned bar_base, unsigned *err, const unsigned *skip,
+                           hipStream_t st)
 {
     switch (B) {
-    case 8: return panel_qr_b<T, 8>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, st);
-    case 16: return panel_qr_b<T, 16>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, st);
-    case 32: return panel_qr_b<T, 32>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, st);
-    case 64: return panel_qr_b<T, 64>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, st);
+    case 8: return panel_qr_b<T, 8>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, skip, st);
+    case 16: return panel_qr_b<T, 16>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, skip, st);
+    case 32: return panel_qr_b<T, 32>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, skip, st);
+    case 64: return panel_qr_b<T, 64>(W, ldw, c0, r0, m, Vd, tau, Tf, part, bar, bar_base, err, skip, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -498,10 +735,27 @@ void launch_band_extract(const T *W, int ldw, int n, int b, double *ab, int ldab
 
 template void launch_ingest<double>(const double *, int, int, double *, int, unsigned *, hipStream_t);
 template void launch_ingest<float>(const double *, int, int, float *, int, unsigned *, hipStream_t);
+void launch_gram_reduce(const double *Gp, int np, int BB, double *G, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gram_reduce, dim3(cdiv(BB, 256)), dim3(256), 0, st, Gp, np, BB, G);
+}
+void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_chol_qr, dim3(1), dim3(256), 0, st, B, pass, cq, flag);
+}
+void launch_hh_rebuild(double *Vd, int m, int B, double *Wp, int ldw, double *cq, double *Tf, double *tau,
+                       const unsigned *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_hh_rebuild, dim3(1), dim3(256), 0, st, Vd, m, B, Wp, ldw, cq, Tf, tau, flag);
+}
+size_t cholqr_scratch_doubles() { return (size_t)6 * 64 * 64; }
+
 template hipError_t launch_panel_qr<double>(double *, int, int, int, int, int, double *, double *, double *,
-                                            double *, unsigned *, unsigned, unsigned *, hipStream_t);
+                                            double *, unsigned *, unsigned, unsigned *, const unsigned *,
+                                            hipStream_t);
 template hipError_t launch_panel_qr<float>(float *, int, int, int, int, int, float *, double *, double *,
-                                           double *, unsigned *, unsigned, unsigned *, hipStream_t);
+                                           double *, unsigned *, unsigned, unsigned *, const unsigned *,
+                                           hipStream_t);
 template void launch_stage1_w<double>(double *, int, int, int, int, const double *, const double *, double *,
                                       double *, double *, double *, double *, hipStream_t);
 template void launch_stage1_w<float>(float *, int, int, int, int, const float *, const double *, float *,

@@ -13,7 +13,17 @@ int panel_qr_groups(int m);
 size_t panel_qr_part_doubles(int m, int B);
 template <typename T>
 hipError_t launch_panel_qr(T *W, int ldw, int c0, int r0, int m, int B, T *Vd, double *tau, double *Tf,
-                           double *part, unsigned *bar, unsigned bar_base, unsigned *err, hipStream_t st);
+                           double *part, unsigned *bar, unsigned bar_base, unsigned *err, const unsigned *skip,
+                           hipStream_t st);
+// Cholesky-QR panel path (FP64): Gram partial reduction, Cholesky step
+// (pass 1 or 2, sets *flag when the panel needs the Householder kernel),
+// Householder reconstruction; scratch cq of cholqr_scratch_doubles().
+constexpr int CQ_G = 0, CQ_R1 = 1, CQ_R1INV = 2, CQ_R2INV = 3, CQ_R = 4, CQ_UINV = 5;
+size_t cholqr_scratch_doubles();
+void launch_gram_reduce(const double *Gp, int np, int BB, double *G, hipStream_t st);
+void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st);
+void launch_hh_rebuild(double *Vd, int m, int B, double *Wp, int ldw, double *cq, double *Tf, double *tau,
+                       const unsigned *flag, hipStream_t st);
 int symm_splits(int m);
 int symm_kchunk(int m, int S);
 int gram_chunk_rows();
@@ -49,7 +59,7 @@ void launch_bt2(T *Z, int ldz, int n, int ncols, int b, int nb2, const double *V
 int tn_splits(int K, int tiles);
 template <typename T>
 int launch_gemm_tn_part(const T *A, int lda, const T *B, int ldb, int M, int N, int K, double *Cpart,
-                        hipStream_t st);
+                        hipStream_t st, int S_req = 0);
 template <typename T>
 void launch_gemm_nn(const T *A, int lda, const double *Bpart, int S, int M, int N, int K, T *C, int ldc,
                     double alpha, int beta, hipStream_t st);
