@@ -25,6 +25,7 @@
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
+#include "small64.h"
 
 namespace {
 
@@ -438,89 +439,90 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ 
 // Cholesky factor R (upper, G = R^T R) and R^{-1} of the Gram matrix in
 // cq[CQ_G].  pass 1: R1, R1^{-1}; flag = 1 when a pivot falls below
 // 1e-13 max_i G_ii (condition of the panel beyond what two passes restore).
-// pass 2 (skipped when the flag is set): R2^{-1} and R = R2 R1; flag = 1 when
-// a pivot of G2 (close to I) leaves [0.5, 2].
+// pass 2 (skipped when the flag is set): R2^{-1} and R = R2 R1.  There
+// G2 = I + E; when max |E_ij| <= 1e-8 the factor is taken to first order,
+// R2 = I + diag(E)/2 + strict upper(E), R2^{-1} = I - diag(E)/2 - strict
+// upper(E), whose neglected terms are O(|E|^2) <= 1e-16; otherwise R2 is
+// factored, and flag = 1 when a pivot leaves (0.5, 2).
 __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__restrict__ cq,
                                                  unsigned *__restrict__ flag)
 {
-    __shared__ double M[64 * 65], X[64 * 65], part[4][64];
+    __shared__ double M[64 * 65], X[64 * 65], R1s[64 * 65], part[4][64], rinv[64];
     __shared__ int bad;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     if (pass == 2 && *flag) return;
     const size_t BB = 64 * 64;
     const double *G = cq + CQ_G * BB;
+    const double *R1 = cq + CQ_R1 * BB;
+    double emax = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
-        M[tx * 65 + j] = (tx < B && j < B) ? G[(size_t)j * B + tx] : 0.0;
-        X[tx * 65 + j] = 0.0;
+        const bool in = tx < B && j < B;
+        const double gv = in ? G[(size_t)j * B + tx] : 0.0;
+        M[tx * 65 + j] = gv;
+        if (pass == 2) {
+            R1s[tx * 65 + j] = in ? R1[(size_t)j * B + tx] : 0.0;
+            if (in) emax = fmax(emax, fabs(gv - ((tx == j) ? 1.0 : 0.0)));
+        }
     }
     if (tid == 0) bad = 0;
+    if (pass == 2) part[ty][tx] = wave_max(emax);
     __syncthreads();
-    double dmax = 0.0;
-    for (int i = 0; i < B; ++i) dmax = fmax(dmax, M[i * 65 + i]);
-    const double lo = (pass == 1) ? 1e-13 * dmax : 0.5, hi = (pass == 1) ? 2.0 * dmax : 2.0;
-    // G = R^T R, R upper in the upper triangle of M, right-looking
-    for (int j = 0; j < B; ++j) {
-        const double d = M[j * 65 + j];
-        if (!(d > lo && d < hi)) {                 // uniform: every thread reads the same d
-            if (tid == 0) bad = 1;
-            break;
-        }
-        const double rjj = sqrt(d), ir = 1.0 / rjj;
-        const double rjr = (tx > j && tx < B) ? M[j * 65 + tx] * ir : 0.0;
-        double rjc[16];
+    bool first_order = false;
+    if (pass == 2) {
+        const double e = fmax(fmax(part[0][0], part[1][0]), fmax(part[2][0], part[3][0]));
+        first_order = e <= 1e-8;
+    }
+    if (first_order) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int c = ty + 4 * q;
-            rjc[q] = (c > j && c < B) ? M[j * 65 + c] * ir : 0.0;
+            const double e = M[tx * 65 + c] - ((tx == c) ? 1.0 : 0.0);
+            const double f = (tx == c) ? 0.5 * e : ((tx < c) ? e : 0.0);
+            X[tx * 65 + c] = ((tx == c) ? 1.0 : 0.0) - f;   // R2^{-1}
         }
         __syncthreads();
-        if (ty == 0) {
-            if (tx == j) M[j * 65 + j] = rjj;
-            else if (tx > j && tx < B) M[j * 65 + tx] = rjr;
-        }
-        if (tx > j && tx < B) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int c = ty + 4 * q;
-                if (c >= tx && c < B) M[tx * 65 + c] -= rjr * rjc[q];
-            }
+        for (int q = 0; q < 16; ++q) {
+            const int c = ty + 4 * q;
+            const double e = M[tx * 65 + c] - ((tx == c) ? 1.0 : 0.0);
+            M[tx * 65 + c] = ((tx == c) ? 1.0 + 0.5 * e : ((tx < c) ? e : 0.0));   // R2 (own elements)
         }
         __syncthreads();
-    }
-    __syncthreads();
-    if (bad) {
-        if (tid == 0) *flag = 1u;
-        return;
-    }
-    // R^{-1} by rows from the bottom; column c = tx, the sum over u split over the four waves
-    for (int i = B - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int u = i + 1 + ty; u <= tx && u < B; u += 4) s += M[i * 65 + u] * X[u * 65 + tx];
-        part[ty][tx] = s;
+    } else {
+        double dmax = 0.0;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) dmax = fmax(dmax, (i < B) ? M[i * 65 + i] : 0.0);
+        const double lo = (pass == 1) ? 1e-13 * dmax : 0.5, hi = (pass == 1) ? 2.0 * dmax : 2.0;
+        const bool ok = eliminate(M, B, true, false, lo, hi, nullptr, &bad);
         __syncthreads();
-        if (ty == 0 && tx < B && i <= tx)
-            X[i * 65 + tx] = (((i == tx) ? 1.0 : 0.0) - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx])) /
-                             M[i * 65 + i];
-        __syncthreads();
+        if (!ok || bad) {
+            if (tid == 0) *flag = 1u;
+            return;
+        }
+        tri_inv_upper(M, X, B, part, rinv);
     }
     double *Ro = cq + ((pass == 1) ? CQ_R1 : CQ_R) * BB;
     double *Ri = cq + ((pass == 1) ? CQ_R1INV : CQ_R2INV) * BB;
-    const double *R1 = cq + CQ_R1 * BB;
+    // pass 2: (R2 R1)[r][c] = sum_{r <= u <= c} R2[r][u] R1[u][c]
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    if (pass == 2) {
+#pragma unroll 8
+        for (int u = 0; u < 64; ++u) {
+            const double a = (u >= tx) ? M[tx * 65 + u] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] += R1s[u * 65 + ty + 4 * q] * a;
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
         if (tx < B && j < B) {
             Ri[(size_t)j * B + tx] = (tx <= j) ? X[tx * 65 + j] : 0.0;
-            double r;
-            if (pass == 1) {
-                r = (tx <= j) ? M[tx * 65 + j] : 0.0;
-            } else {                               // (R2 R1)[tx][j] = sum_{tx <= u <= j} R2[tx][u] R1[u][j]
-                r = 0.0;
-                for (int u = tx; u <= j; ++u) r += M[tx * 65 + u] * R1[(size_t)j * B + u];
-            }
-            Ro[(size_t)j * B + tx] = r;
+            Ro[(size_t)j * B + tx] = (tx <= j) ? ((pass == 1) ? M[tx * 65 + j] : acc[q]) : 0.0;
         }
     }
     if (pass == 1 && tid == 0) *flag = 0u;
@@ -534,7 +536,8 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(double *__restrict__ Vd, int
                                                     int ldw, double *__restrict__ cq, double *__restrict__ Tf,
                                                     double *__restrict__ tau, const unsigned *__restrict__ flag)
 {
-    __shared__ double M[64 * 65], X[64 * 65], Y[64 * 65], sgn[64], part[4][64];
+    __shared__ double M[64 * 65], X[64 * 65], Ts[64 * 65], sgn[64], part[4][64], rinv[64];
+    __shared__ int bad;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     if (*flag) return;
     const size_t BB = 64 * 64;
@@ -542,70 +545,28 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(double *__restrict__ Vd, int
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
         M[tx * 65 + j] = (tx < B && j < B) ? Vd[(size_t)j * m + tx] : 0.0;
+        Ts[tx * 65 + j] = 0.0;
     }
+    if (tid < 64) sgn[tid] = 0.0;
     __syncthreads();
-    // LU of Q_top - S without pivoting: L unit lower (below the diagonal of
-    // M), U upper (on and above it)
-    for (int i = 0; i < B; ++i) {
-        const double p0 = M[i * 65 + i];
-        const double si = (p0 >= 0.0) ? -1.0 : 1.0;
-        const double piv = p0 - si, ip = 1.0 / piv;
-        const double lr = (tx > i && tx < B) ? M[tx * 65 + i] * ip : 0.0;
-        double ur[16];
+    eliminate(M, B, false, false, 0.0, 0.0, sgn, &bad);
+    tri_inv_upper(M, X, B, part, rinv);            // X = U^{-1}
+    // T = -U S L^{-T} by columns: T[r][c] = -u_rc s_c - sum_{r <= k < c} T[r][k] l_ck
+    for (int c = 0; c < B; ++c) {
+        double s = 0.0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int c = ty + 4 * q;
-            ur[q] = (c > i && c < B) ? M[i * 65 + c] : 0.0;
+            const int k = ty + 4 * q;
+            const double t = Ts[tx * 65 + k], l = M[c * 65 + k];
+            s += (k >= tx && k < c) ? t * l : 0.0;
         }
-        __syncthreads();
-        if (tid == 0) {
-            M[i * 65 + i] = piv;
-            sgn[i] = si;
-        }
-        if (ty == 0 && tx > i && tx < B) M[tx * 65 + i] = lr;
-        if (tx > i && tx < B) {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int c = ty + 4 * q;
-                if (c > i && c < B) M[tx * 65 + c] -= lr * ur[q];
-            }
-        }
-        __syncthreads();
-    }
-    // X = U^{-1} (rows from the bottom; column tx, the sum over u split over
-    // the four waves), Y = L^{-1} (rows from the top)
-    for (int i = B - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int u = i + 1 + ty; u <= tx && u < B; u += 4) s += M[i * 65 + u] * X[u * 65 + tx];
         part[ty][tx] = s;
         __syncthreads();
-        if (ty == 0 && tx < B)
-            X[i * 65 + tx] = (i <= tx) ? (((i == tx) ? 1.0 : 0.0) - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx])) /
-                                             M[i * 65 + i]
-                                       : 0.0;
+        if (ty == 0 && tx <= c)
+            Ts[tx * 65 + c] = -M[tx * 65 + c] * sgn[c] - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx]);
         __syncthreads();
     }
-    for (int i = 0; i < B; ++i) {
-        double s = 0.0;
-        if (ty == 0 && tx < B) {
-            for (int u = 0; u < i; ++u) s += M[i * 65 + u] * Y[u * 65 + tx];
-            Y[i * 65 + tx] = (i == tx) ? 1.0 : ((i > tx) ? -s : 0.0);
-        }
-        __syncthreads();
-    }
-    // T = -U S L^{-T}:  T[r][c] = -sum_{r <= k <= c} U[r][k] s_k Linv[c][k]
-    double *Tout = Tf;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int c = ty + 4 * q, r = tx;
-        if (r < B && c < B) {
-            double t = 0.0;
-            for (int k = r; k <= c; ++k) t += M[r * 65 + k] * sgn[k] * Y[c * 65 + k];
-            Tout[(size_t)c * B + r] = (r <= c) ? -t : 0.0;
-            if (r == c) tau[r] = -t;
-        }
-    }
-    // V top block (unit lower), U^{-1}, R_h = S R (upper triangle of the top block)
+    // outputs: V top block (unit lower), T, tau, U^{-1}, R_h = S R (upper triangle of the top block)
     const double *R = cq + CQ_R * BB;
     double *Ui = cq + CQ_UINV * BB;
 #pragma unroll
@@ -614,6 +575,8 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(double *__restrict__ Vd, int
         if (r < B && c < B) {
             Vd[(size_t)c * m + r] = (r > c) ? M[r * 65 + c] : ((r == c) ? 1.0 : 0.0);
             Ui[(size_t)c * B + r] = (r <= c) ? X[r * 65 + c] : 0.0;
+            Tf[(size_t)c * B + r] = (r <= c) ? Ts[r * 65 + c] : 0.0;
+            if (r == c) tau[r] = Ts[r * 65 + r];
             if (r <= c) Wp[(size_t)c * ldw + r] = sgn[r] * R[(size_t)c * B + r];
         }
     }

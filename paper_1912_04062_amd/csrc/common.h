@@ -175,6 +175,13 @@ __device__ __forceinline__ void sum_partials_2d(const double *__restrict__ P, in
     }
 }
 
+// Wavefront maximum (64 lanes) via cross-lane shuffles.
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // Wavefront sum (64 lanes) via cross-lane shuffles.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)

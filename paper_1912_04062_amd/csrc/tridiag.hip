@@ -21,6 +21,7 @@
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
+#include "small64.h"
 
 namespace {
 
@@ -321,67 +322,28 @@ __global__ void k_transpose(const double *__restrict__ Y, int n, int nev, const 
     }
 }
 
-// Cholesky of G = sum of partials (NB x NB, NB <= 64) and R^{-1} (upper).
-// Thread (tx, ty) = (tid % 64, tid / 64) owns row tx and columns ty + 4q.
+// Cholesky of G = sum of partials (NB x NB, NB <= 64) and R^{-1} (upper);
+// a non-positive pivot is replaced by 1e-300.
 __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp, int nparts, int NB,
                                                   double *__restrict__ Rinv)
 {
-    __shared__ double G[64 * 65], R[64 * 65], part[4][64];
+    __shared__ double G[64 * 65], X[64 * 65], part[4][64], rinv[64];
+    __shared__ int bad;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     {
         double acc[16];
         sum_partials_2d(Gp, nparts, (size_t)NB * NB,
                         [=](int i, int j) -> int { return (i < NB && j < NB) ? j * NB + i : -1; }, acc);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            G[tx * 65 + ty + 4 * q] = acc[q];        // G[i][j]
-            R[tx * 65 + ty + 4 * q] = 0.0;
-        }
+        for (int q = 0; q < 16; ++q) G[tx * 65 + ty + 4 * q] = acc[q];   // G[i][j]
     }
     __syncthreads();
-    // G = R^T R, R upper (kept in the upper triangle of G), right-looking
-    for (int j = 0; j < NB; ++j) {
-        const double d = G[j * 65 + j];
-        const double rjj = sqrt(d > 0.0 ? d : 1e-300);
-        // row j of R, read before the barrier by every thread
-        const double rjr = (tx > j) ? G[j * 65 + tx] / rjj : 0.0;
-        double rjc[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int c = ty + 4 * q;
-            rjc[q] = (c > j && c < NB) ? G[j * 65 + c] / rjj : 0.0;
-        }
-        __syncthreads();
-        if (ty == 0) {
-            if (tx == j) G[j * 65 + j] = rjj;
-            else if (tx > j && tx < NB) G[j * 65 + tx] = rjr;
-        }
-        if (tx > j && tx < NB) {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int c = ty + 4 * q;
-                if (c >= tx && c < NB) G[tx * 65 + c] -= rjr * rjc[q];
-            }
-        }
-        __syncthreads();
-    }
-    // R^{-1} by rows from the bottom: X[i][c] = (delta_ic - sum_{u>i} R[i][u] X[u][c]) / R[i][i];
-    // column c = tx, the sum over u split over the four waves
-    for (int i = NB - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int u = i + 1 + ty; u <= tx && u < NB; u += 4) s += G[i * 65 + u] * R[u * 65 + tx];
-        part[ty][tx] = s;
-        __syncthreads();
-        if (ty == 0 && tx < NB) {
-            const double tot = part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx];
-            R[i * 65 + tx] = (i <= tx) ? (((i == tx) ? 1.0 : 0.0) - tot) / G[i * 65 + i] : 0.0;
-        }
-        __syncthreads();
-    }
+    eliminate(G, NB, true, true, 0.0, 0.0, nullptr, &bad);
+    tri_inv_upper(G, X, NB, part, rinv);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
-        if (tx < NB && j < NB) Rinv[(size_t)j * NB + tx] = R[tx * 65 + j];   // column-major
+        if (tx < NB && j < NB) Rinv[(size_t)j * NB + tx] = (tx <= j) ? X[tx * 65 + j] : 0.0;   // column-major
     }
 }
 
