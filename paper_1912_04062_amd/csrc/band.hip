@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__rest
 #pragma unroll
         for (int i = 0; i < 64; ++i) dmax = fmax(dmax, (i < B) ? M[i * 65 + i] : 0.0);
         const double lo = (pass == 1) ? 1e-13 * dmax : 0.5, hi = (pass == 1) ? 2.0 * dmax : 2.0;
-        const bool ok = eliminate(M, B, true, false, lo, hi, nullptr, &bad);
+        const bool ok = cholesky64(M, B, false, lo, hi, &bad);
         __syncthreads();
         if (!ok || bad) {
             if (tid == 0) *flag = 1u;
@@ -549,18 +549,19 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(double *__restrict__ Vd, int
     }
     if (tid < 64) sgn[tid] = 0.0;
     __syncthreads();
-    eliminate(M, B, false, false, 0.0, 0.0, sgn, &bad);
+    lu_signed64(M, B, sgn);
     tri_inv_upper(M, X, B, part, rinv);            // X = U^{-1}
     // T = -U S L^{-T} by columns: T[r][c] = -u_rc s_c - sum_{r <= k < c} T[r][k] l_ck
     for (int c = 0; c < B; ++c) {
-        double s = 0.0;
+        // Ts is zero below the diagonal and in columns >= c: no masks
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < 16; q += 2) {
             const int k = ty + 4 * q;
-            const double t = Ts[tx * 65 + k], l = M[c * 65 + k];
-            s += (k >= tx && k < c) ? t * l : 0.0;
+            s0 = fma(Ts[tx * 65 + k], M[c * 65 + k], s0);
+            s1 = fma(Ts[tx * 65 + k + 4], M[c * 65 + k + 4], s1);
         }
-        part[ty][tx] = s;
+        part[ty][tx] = s0 + s1;
         __syncthreads();
         if (ty == 0 && tx <= c)
             Ts[tx * 65 + c] = -M[tx * 65 + c] * sgn[c] - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx]);

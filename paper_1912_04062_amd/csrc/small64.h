@@ -9,7 +9,11 @@
 namespace {
 
 // X = R^{-1} for R upper triangular (B x B), rows of X from the bottom:
-// X[i][c] = (delta_ic - sum_{i < u <= c} R[i][u] X[u][c]) / R[i][i].
+// X[i][c] = (delta_ic - sum_{i < u <= c} R[i][u] X[u][c]) / R[i][i].  X
+// starts at zero and row i is written at step i, so at that step X[u][c] is
+// zero for u <= i and for u > c: the sum runs over all u with no masks.
+// The strict lower triangle of R is read (multiplied by zeros): it must hold
+// finite values.
 __device__ __forceinline__ void tri_inv_upper(const double *R, double *X, int B, double (*part)[64], double *rinv)
 {
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
@@ -18,14 +22,14 @@ __device__ __forceinline__ void tri_inv_upper(const double *R, double *X, int B,
     for (int q = 0; q < 16; ++q) X[tx * 65 + ty + 4 * q] = 0.0;
     __syncthreads();
     for (int i = B - 1; i >= 0; --i) {
-        double s = 0.0;
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < 16; q += 2) {
             const int u = ty + 4 * q;
-            const double a = R[i * 65 + u], x = X[u * 65 + tx];
-            s += (u > i && u <= tx && u < B) ? a * x : 0.0;
+            s0 = fma(R[i * 65 + u], X[u * 65 + tx], s0);
+            s1 = fma(R[i * 65 + u + 4], X[(u + 4) * 65 + tx], s1);
         }
-        part[ty][tx] = s;
+        part[ty][tx] = s0 + s1;
         __syncthreads();
         if (ty == 0 && tx < B && i <= tx)
             X[i * 65 + tx] = (((i == tx) ? 1.0 : 0.0) - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx])) * rinv[i];
@@ -33,61 +37,73 @@ __device__ __forceinline__ void tri_inv_upper(const double *R, double *X, int B,
     }
 }
 
-// Right-looking elimination of the B x B matrix M in place (64 steps).
-// Cholesky (chol = true): M = R^T R, R upper in the upper triangle; returns
-// false when a pivot leaves (lo, hi), or, with clamp, replaces a pivot
-// <= 0 by 1e-300 and never fails.  LU (chol = false): M - S = L U with
-// s_i = -sign(pivot) chosen at step i (sgn[i]); L unit lower below the
-// diagonal, U on and above it (|u_ii| >= 1, no pivoting).
-__device__ __forceinline__ bool eliminate(double *M, int B, bool chol, bool clamp, double lo, double hi, double *sgn,
-                                          int *bad)
+// Cholesky M = R^T R of the symmetric positive B x B matrix M in place (64
+// steps, right-looking, both triangles updated): step j scales row j by
+// 1/r_jj and subtracts R[j][r] R[j][c] from every element (r, c) with r > j.
+// R ends in the upper triangle, the strict lower triangle tends to zero
+// (finite).  Returns false when a pivot leaves (lo, hi); with clamp a pivot
+// <= 0 is replaced by 1e-300 and the factorization never fails.  Rows and
+// columns B..63 must be zero.
+__device__ __forceinline__ bool cholesky64(double *M, int B, bool clamp, double lo, double hi, int *bad)
 {
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     for (int j = 0; j < B; ++j) {
         const double d = M[j * 65 + j];
-        double piv, si = 0.0;
-        if (chol) {
-            if (!clamp && !(d > lo && d < hi)) {   // uniform: every thread reads the same d
-                if (tid == 0) *bad = 1;
-                return false;
-            }
-            piv = sqrt((clamp && !(d > 0.0)) ? 1e-300 : d);
-        } else {
-            si = (d >= 0.0) ? -1.0 : 1.0;
-            piv = d - si;
+        if (!clamp && !(d > lo && d < hi)) {   // uniform: every thread reads the same d
+            if (tid == 0) *bad = 1;
+            return false;
         }
-        const double ip = 1.0 / piv;
-        // Cholesky: row j of R is M[j][c] / r_jj and row r is updated with
-        // R[j][r] R[j][c]; LU: multipliers l_r = M[r][j] / u_jj, row j of U
-        // unchanged
-        const double lr = (chol ? M[j * 65 + tx] : M[tx * 65 + j]) * ip;
+        const double ip = 1.0 / sqrt((clamp && !(d > 0.0)) ? 1e-300 : d);
+        const double lr = (tx > j) ? M[j * 65 + tx] * ip : 0.0;   // R[j][tx] for rows below j
+        const double a = (tx == j) ? ip : 1.0;                      // row j: scaled by 1/r_jj
+        double rc[16], old[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            rc[q] = M[j * 65 + ty + 4 * q];
+            old[q] = M[tx * 65 + ty + 4 * q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) M[tx * 65 + ty + 4 * q] = fma(-lr, rc[q] * ip, old[q] * a);
+        __syncthreads();
+    }
+    return true;
+}
+
+// LU factorization M - S = L U without pivoting, S = diag(s_i) with
+// s_i = -sign of the pivot met at step i (so |u_ii| >= 1); s_i goes to
+// sgn[i].  L (unit lower) ends below the diagonal, U on and above it.  Rows
+// and columns B..63 must be zero.
+__device__ __forceinline__ void lu_signed64(double *M, int B, double *sgn)
+{
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    for (int j = 0; j < B; ++j) {
+        const double d = M[j * 65 + j];
+        const double si = (d >= 0.0) ? -1.0 : 1.0, piv = d - si, ip = 1.0 / piv;
+        // rows below j: multiplier l = M[r][j] / u_jj; column j receives l
+        // itself (old - l (u_jj - 1) = l), columns right of j the update, the
+        // columns left of j (earlier multipliers) nothing
+        const double lr = (tx > j) ? M[tx * 65 + j] * ip : 0.0;
         double rc[16], old[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int c = ty + 4 * q;
-            rc[q] = M[j * 65 + c] * (chol ? ip : 1.0);
+            const double u = M[j * 65 + c];
+            rc[q] = (c > j) ? u : ((c == j) ? piv - 1.0 : 0.0);
             old[q] = M[tx * 65 + c];
         }
         __syncthreads();
-        const bool live = tx < B;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int c = ty + 4 * q;
-            double v = old[q];
-            if (chol) {
-                if (tx == j) v = (c == j) ? piv : ((c > j) ? rc[q] : v);
-                else if (tx > j && c >= tx && c < B) v = old[q] - lr * rc[q];
-            } else {
-                if (tx == j && c == j) v = piv;
-                else if (tx > j && c == j) v = lr;
-                else if (tx > j && c > j && c < B) v = old[q] - lr * rc[q];
-            }
-            M[tx * 65 + c] = live ? v : old[q];
-        }
-        if (!chol && tid == 0) sgn[j] = si;
+        for (int q = 0; q < 16; ++q) M[tx * 65 + ty + 4 * q] = fma(-lr, rc[q], old[q]);
+        if (tid == 0) sgn[j] = si;
         __syncthreads();
     }
-    return true;
+    // row j was left at the pivot d = u_jj + s_j
+    for (int q = 0; q < 16; ++q) {
+        const int c = ty + 4 * q;
+        if (c == tx && c < B) M[c * 65 + c] -= sgn[c];
+    }
+    __syncthreads();
 }
 
 }  // namespace

@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp,
         for (int q = 0; q < 16; ++q) G[tx * 65 + ty + 4 * q] = acc[q];   // G[i][j]
     }
     __syncthreads();
-    eliminate(G, NB, true, true, 0.0, 0.0, nullptr, &bad);
+    cholesky64(G, NB, true, 0.0, 0.0, &bad);
     tri_inv_upper(G, X, NB, part, rinv);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
