@@ -295,10 +295,12 @@ constexpr int PV = 6, PT = 4;
 constexpr int CV = 128 + PV, CT = 128 + PT;     // chunk strides
 constexpr int BUF = 32 * CV + 32 * CT;          // one buffer (V then T)
 
-// V then T of group g into Vl / Tl: wave w moves chunks 16w .. 16w + 15
-// (0..31 of V, then 0..31 of T), 16 bytes per lane.
-__device__ __forceinline__ void prefetch(const double *__restrict__ V2, const double *__restrict__ T2, size_t g,
-                                         double *Vl, double *Tl)
+// Part i (0..7) of the move of group g's V then T into Vl / Tl: wave w moves
+// chunks 16w + 2i and 16w + 2i + 1 (0..31 of V, then 0..31 of T), 16 bytes
+// per lane.  The eight parts are issued between the MFMAs of the preceding
+// group's first phase.
+__device__ __forceinline__ void prefetch_part(const double *__restrict__ V2, const double *__restrict__ T2, size_t g,
+                                              double *Vl, double *Tl, int i)
 {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -307,9 +309,16 @@ __device__ __forceinline__ void prefetch(const double *__restrict__ V2, const do
     const int cs = (wv < 2) ? CV : CT;
     const int c0 = (wv & 1) * 16;
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
+    for (int j = 2 * i; j < 2 * i + 2; ++j)
         __builtin_amdgcn_global_load_lds((gbl_void *)(src + (size_t)(c0 + j) * 128 + 2 * lane),
                                          (lds_void *)(dst + (c0 + j) * cs), 16, 0, 0);
+}
+
+__device__ __forceinline__ void prefetch(const double *__restrict__ V2, const double *__restrict__ T2, size_t g,
+                                         double *Vl, double *Tl)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) prefetch_part(V2, T2, g, Vl, Tl, i);
 }
 
 __device__ __forceinline__ bool blk_ok(int x, int n) { return x >= 0 && 1 + 64 * x < n; }
@@ -375,8 +384,10 @@ __device__ __forceinline__ void store_block(const d4 (&zb)[4], double *__restric
 // alive across the group loop.  Each phase runs its k-steps outermost so that
 // MFMAs of independent output tiles follow each other, and loads the LDS
 // operands of a chunk of k-steps before the chunk's MFMAs.
-template <int S0, int S1>
-__device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl)
+// hook1(i) runs before the i-th chunk of the first phase's k-steps (i = 0..7),
+// pinned there so that its memory instructions issue between MFMAs.
+template <int S0, int S1, class H1>
+__device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl, const H1 &hook1)
 {
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));
@@ -390,6 +401,9 @@ __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl
     for (int mt = 0; mt < 4; ++mt) w1[mt] = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kc = 0; kc < 32; kc += 4) {
+        __builtin_amdgcn_sched_barrier(0);
+        hook1(kc >> 2);
+        __builtin_amdgcn_sched_barrier(0);
         double a[4][4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
@@ -521,9 +535,13 @@ __global__ __launch_bounds__(256) void k_bt2_win(double *__restrict__ Z, int ldz
             ++cur_tau;
             load_block(nxt, Z, ldz, n, col0, ncl, cur_sh + cur_tau + 2);
         }
-        if (nx.sh >= 0) prefetch(V2, T2, gid(nx, goff), Vl(buf ^ 1), Tl(buf ^ 1));
-        if (c.w == 0) apply<2, 3>(w, Vl(buf), Tl(buf));
-        else apply<0, 1>(w, Vl(buf), Tl(buf));
+        // the next group's V and T move into the other buffer during this
+        // group's first phase (the last group re-fetches itself: harmless)
+        const size_t gn = gid(nx.sh >= 0 ? nx : c, goff);
+        double *vn = Vl(buf ^ 1), *tn = Tl(buf ^ 1);
+        auto pf = [&](int i) { prefetch_part(V2, T2, gn, vn, tn, i); };
+        if (c.w == 0) apply<2, 3>(w, Vl(buf), Tl(buf), pf);
+        else apply<0, 1>(w, Vl(buf), Tl(buf), pf);
         wait_vmem();
         __syncthreads();
         buf ^= 1;
