@@ -633,8 +633,10 @@ hipError_t launch_panel_qr(T *W, int ldw, int c0, int r0, int m, int B, T *Vd, d
 
 int symm_splits(int m)
 {
+    // about 16 workgroups per CU: the long K loops of few row tiles leave
+    // the MFMA pipes idle otherwise
     int rows = (int)cdiv(m, 64);
-    int S = (int)cdiv(1024, rows > 0 ? rows : 1);
+    int S = (int)cdiv(4096, rows > 0 ? rows : 1);
     int maxS = (int)cdiv(m, 256);
     if (S > maxS) S = maxS;
     if (S > 16) S = 16;
