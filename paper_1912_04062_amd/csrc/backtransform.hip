@@ -46,38 +46,47 @@ __global__ __launch_bounds__(256) void k_bt2_tfac(const double *__restrict__ V2,
                                                   int rowmajor)
 {
     __shared__ double Vs[64 * 65];       // Vs[r][i]
-    __shared__ double Gm[64 * 65];       // Gram (upper)
+    __shared__ double Gm[64 * 65];       // Gram (strict upper; zero elsewhere)
     __shared__ double Tm[64 * 65];
-    __shared__ double tv[64];
+    __shared__ double tv[64], part[4][64];
     const size_t g = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const double *Vg = V2 + g * (size_t)b * nb2;
     for (int e = tid; e < b * nb2; e += 256) {
         int r = e % b, i = e / b;
         Vs[r * 65 + i] = Vg[e];
         if (V2t) V2t[g * (size_t)b * nb2 + e] = (T)Vg[e];
     }
-    if (tid < nb2) tv[tid] = tau2[g * nb2 + tid];
+    if (tid < 64) tv[tid] = (tid < nb2) ? tau2[g * nb2 + tid] : 0.0;
     for (int e = tid; e < 64 * 65; e += 256) Tm[e] = 0.0;
     __syncthreads();
     // Gram: v_i . v_j (i < j), overlap rows j..i+b-1 (absolute), r = row - i
-    for (int e = tid; e < nb2 * nb2; e += 256) {
-        int i = e % nb2, j = e / nb2;
-        if (i < j) {
+    for (int e = tid; e < 64 * 64; e += 256) {
+        int i = e % 64, j = e / 64;
+        double s = 0.0;
+        if (i < j && j < nb2) {
             int d = j - i;
-            double s = 0.0;
             for (int r = d; r < b; ++r) s += Vs[r * 65 + i] * Vs[(r - d) * 65 + j];
-            Gm[i * 65 + j] = s;
         }
+        Gm[i * 65 + j] = s;
     }
     __syncthreads();
+    // T[i][j] = -tau_j sum_{i <= u < j} T[i][u] G[u][j], T[j][j] = tau_j.  T
+    // starts at zero and column u is written at step u, so the sum runs over
+    // all u (G is zero on and below the diagonal); the four wavefronts take
+    // a quarter of the u each.
     for (int j = 0; j < nb2; ++j) {
-        if (tid < j) {
-            double s = 0.0;
-            for (int u = tid; u < j; ++u) s += Tm[tid * 65 + u] * Gm[u * 65 + j];
-            Tm[tid * 65 + j] = -tv[j] * s;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; q += 2) {
+            const int u = ty + 4 * q;
+            s0 = fma(Tm[tx * 65 + u], Gm[u * 65 + j], s0);
+            s1 = fma(Tm[tx * 65 + u + 4], Gm[(u + 4) * 65 + j], s1);
         }
-        if (tid == j) Tm[j * 65 + j] = tv[j];
+        part[ty][tx] = s0 + s1;
+        __syncthreads();
+        if (ty == 0 && tx <= j)
+            Tm[tx * 65 + j] = (tx == j) ? tv[j] : -tv[j] * (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx]);
         __syncthreads();
     }
     T *To = T2 + g * (size_t)nb2 * nb2;

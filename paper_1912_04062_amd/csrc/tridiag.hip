@@ -323,19 +323,40 @@ __global__ void k_transpose(const double *__restrict__ Y, int n, int nev, const 
 }
 
 // Cholesky of G = sum of partials (NB x NB, NB <= 64) and R^{-1} (upper);
-// a non-positive pivot is replaced by 1e-300.
+// a non-positive pivot is replaced by 1e-300.  When G = I + E with
+// max |E_ij| <= 1e-8 (a block already orthonormal to that level) R^{-1} is
+// taken to first order, I - diag(E)/2 - strict upper(E); the neglected terms
+// are O(|E|^2) <= 1e-16.
 __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp, int nparts, int NB,
                                                   double *__restrict__ Rinv)
 {
     __shared__ double G[64 * 65], X[64 * 65], part[4][64], rinv[64];
     __shared__ int bad;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    double emax = 0.0;
     {
         double acc[16];
         sum_partials_2d(Gp, nparts, (size_t)NB * NB,
                         [=](int i, int j) -> int { return (i < NB && j < NB) ? j * NB + i : -1; }, acc);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) G[tx * 65 + ty + 4 * q] = acc[q];   // G[i][j]
+        for (int q = 0; q < 16; ++q) {
+            const int j = ty + 4 * q;
+            G[tx * 65 + j] = acc[q];   // G[i][j]
+            if (tx < NB && j < NB) emax = fmax(emax, fabs(acc[q] - ((tx == j) ? 1.0 : 0.0)));
+        }
+    }
+    part[ty][tx] = wave_max(emax);
+    __syncthreads();
+    if (fmax(fmax(part[0][0], part[1][0]), fmax(part[2][0], part[3][0])) <= 1e-8) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = ty + 4 * q;
+            if (tx < NB && j < NB) {
+                const double e = G[tx * 65 + j] - ((tx == j) ? 1.0 : 0.0);
+                Rinv[(size_t)j * NB + tx] = (tx == j) ? 1.0 - 0.5 * e : ((tx < j) ? -e : 0.0);
+            }
+        }
+        return;
     }
     __syncthreads();
     cholesky64(G, NB, true, 0.0, 0.0, &bad);
