@@ -58,6 +58,18 @@ __global__ void k_alpha2(const double *__restrict__ alpha, int n, double *__rest
     }
 }
 
+// 1/d for a normal d (|d| >= pivmin): the hardware estimate refined by two
+// Newton steps r <- r (2 - d r), each of which squares the relative error,
+// so the result is within an ulp or two of the rounded quotient -- the
+// small relative perturbation of each pivot that the Sturm count tolerates.
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
 // 256 threads = 16 eigenvalues x 16 shifts.  Eigenvalue index first + e.
 __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, int n, int first, int count,
                                                 const double *__restrict__ stats, int rounds,
@@ -85,7 +97,7 @@ __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, i
             for (int i = threadIdx.x; i < len; i += 256) sa[i] = a2[c0 + i];
             __syncthreads();
             for (int i = 0; i < len; ++i) {
-                d = -xq - sa[i] / d;
+                d = -xq - sa[i] * recip(d);
                 if (fabs(d) < pivmin) d = -pivmin;
                 cnt += (d < 0.0) ? 1 : 0;
             }
@@ -121,7 +133,8 @@ __device__ __forceinline__ double hash_uniform(unsigned long long seed, unsigned
 // Inverse iteration, one thread per vector (one wavefront per workgroup so
 // that the vectors spread over as many CUs as possible).  Workspace (each
 // n x nev, [i][k] layout, so a wavefront's accesses are contiguous):
-// U0, U1, U2 (rows of U; U0 already clamped away from 0), Lm (multipliers),
+// U0, U1, U2 (rows of U; U0 holds the reciprocals of the pivots, which are
+// clamped away from 0), Lm (multipliers),
 // Sw (row swaps), Y (iterate).  Every pass runs in chunks of IV_CH steps
 // whose loads are all issued before the chunk's sequential arithmetic.
 // The iterate is normalised on the fly (its norm is accumulated by the
@@ -168,24 +181,27 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
                 const int i = i0 + j;
                 if (i + 1 >= n) continue;           // predicated (no break: keeps the loop unrolled)
                 const double sub = al[j], dn = -shift, en = al[j + 1];
+                // the pivot is clamped away from 0 (the factorization is
+                // that of T - shift I perturbed by at most tiny) and stored
+                // as its reciprocal
                 if (fabs(a) >= fabs(sub)) {
-                    if (a == 0.0) a = tiny;
-                    const double l = sub / a;
+                    const double r = recip(clampu(a));
+                    const double l = sub * r;
                     Sw[i * st + k] = 0;
                     Lm[i * st + k] = l;
-                    U0[i * st + k] = clampu(a); U1[i * st + k] = bb; U2[i * st + k] = cc;
+                    U0[i * st + k] = r; U1[i * st + k] = bb; U2[i * st + k] = cc;
                     a = dn - l * bb; bb = en - l * cc; cc = 0.0;
                 } else {
-                    const double l = a / sub;
+                    const double r = recip(clampu(sub));
+                    const double l = a * r;
                     Sw[i * st + k] = 1;
                     Lm[i * st + k] = l;
-                    U0[i * st + k] = clampu(sub); U1[i * st + k] = dn; U2[i * st + k] = en;
+                    U0[i * st + k] = r; U1[i * st + k] = dn; U2[i * st + k] = en;
                     a = bb - l * dn; bb = cc - l * en; cc = 0.0;
                 }
             }
         }
-        if (fabs(a) < tiny) a = (a < 0.0) ? -tiny : tiny;
-        U0[(size_t)(n - 1) * st + k] = a;
+        U0[(size_t)(n - 1) * st + k] = recip(clampu(a));
     }
     // norm of the generated start vector
     double inv;
@@ -251,7 +267,7 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
                 const int i = i1 - j;
                 if (i < 0) continue;
                 // U1, U2 of the last rows are never written: they multiply x1 = x2 = 0
-                const double xi = (rv[j] - ((i + 1 < n) ? u1[j] : 0.0) * x1 - ((i + 2 < n) ? u2[j] : 0.0) * x2) / u0[j];
+                const double xi = (rv[j] - ((i + 1 < n) ? u1[j] : 0.0) * x1 - ((i + 2 < n) ? u2[j] : 0.0) * x2) * u0[j];
                 Y[i * st + k] = xi;
                 if (i & 1) so += xi * xi;
                 else se += xi * xi;
