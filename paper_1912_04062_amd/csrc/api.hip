@@ -320,25 +320,27 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
         double *tauj = ptr<double>(h, L.tauall) + (size_t)j * b;
         HCHK(kt_begin(h, SKEW_EVD_K_PANEL));
         const unsigned *skip = nullptr;
-        if (sizeof(T) == sizeof(double) && m >= b) {
-            // Cholesky QR twice + Householder reconstruction; the Householder
-            // panel kernel below runs only when this path flags the panel
-            double *P = (double *)(void *)W + (size_t)c0 * n + r0;
-            double *Vq = (double *)(void *)Vd;
+        if (m >= b) {
+            // Cholesky QR twice + Householder reconstruction (Gram matrices
+            // and the small factorizations in FP64 also in the FP32 form); the
+            // Householder panel kernel below runs only when this path flags
+            // the panel
+            T *P = W + (size_t)c0 * n + r0;
+            T *Vq = Vd;
             double *cq = ptr<double>(h, L.cq), *Gq = ptr<double>(h, L.cqGp);
             unsigned *qf = ctl + CTL_QRFLAG;
             const size_t BB = (size_t)64 * 64;
-            int S = skew::launch_gemm_tn_part<double>(P, n, P, n, b, b, m, Gq, st, cholqr_splits(m));
+            int S = skew::launch_gemm_tn_part<T>(P, n, P, n, b, b, m, Gq, st, cholqr_splits(m));
             skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
             skew::launch_chol_qr(b, 1, cq, qf, st);
-            skew::launch_gemm_nn<double>(P, n, cq + skew::CQ_R1INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
-            S = skew::launch_gemm_tn_part<double>(Vq, m, Vq, m, b, b, m, Gq, st, cholqr_splits(m));
+            skew::launch_gemm_nn<T>(P, n, cq + skew::CQ_R1INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
+            S = skew::launch_gemm_tn_part<T>(Vq, m, Vq, m, b, b, m, Gq, st, cholqr_splits(m));
             skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
             skew::launch_chol_qr(b, 2, cq, qf, st);
-            skew::launch_gemm_nn<double>(Vq, m, cq + skew::CQ_R2INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
-            skew::launch_hh_rebuild(Vq, m, b, P, n, cq, Tf, tauj, qf, st);
+            skew::launch_gemm_nn<T>(Vq, m, cq + skew::CQ_R2INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
+            skew::launch_hh_rebuild<T>(Vq, m, b, P, n, cq, Tf, tauj, qf, st);
             if (m > b)
-                skew::launch_gemm_nn<double>(Vq + b, m, cq + skew::CQ_UINV * BB, 1, m - b, b, b, Vq + b, m, 1.0, 0, st);
+                skew::launch_gemm_nn<T>(Vq + b, m, cq + skew::CQ_UINV * BB, 1, m - b, b, b, Vq + b, m, 1.0, 0, st);
             skip = qf;
         }
         HCHK(skew::launch_panel_qr<T>(W, n, c0, r0, m, b, Vd, tauj, Tf, ptr<double>(h, L.part), ctl + CTL_BAR,

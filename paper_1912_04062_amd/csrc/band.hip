@@ -532,7 +532,8 @@ __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__rest
 // writes V's top block L into Vd, T into Tf (column-major), tau = diag(T),
 // R_h = S R into the panel's top block of W (upper triangle), U^{-1} into
 // cq[CQ_UINV].  Nothing is done when the flag is set.
-__global__ __launch_bounds__(256) void k_hh_rebuild(double *__restrict__ Vd, int m, int B, double *__restrict__ Wp,
+template <typename T>
+__global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, int B, T *__restrict__ Wp,
                                                     int ldw, double *__restrict__ cq, double *__restrict__ Tf,
                                                     double *__restrict__ tau, const unsigned *__restrict__ flag)
 {
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(double *__restrict__ Vd, int
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
-        M[tx * 65 + j] = (tx < B && j < B) ? Vd[(size_t)j * m + tx] : 0.0;
+        M[tx * 65 + j] = (tx < B && j < B) ? (double)Vd[(size_t)j * m + tx] : 0.0;
         Ts[tx * 65 + j] = 0.0;
     }
     if (tid < 64) sgn[tid] = 0.0;
@@ -574,11 +575,11 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(double *__restrict__ Vd, int
     for (int q = 0; q < 16; ++q) {
         const int c = ty + 4 * q, r = tx;
         if (r < B && c < B) {
-            Vd[(size_t)c * m + r] = (r > c) ? M[r * 65 + c] : ((r == c) ? 1.0 : 0.0);
+            Vd[(size_t)c * m + r] = (T)((r > c) ? M[r * 65 + c] : ((r == c) ? 1.0 : 0.0));
             Ui[(size_t)c * B + r] = (r <= c) ? X[r * 65 + c] : 0.0;
             Tf[(size_t)c * B + r] = (r <= c) ? Ts[r * 65 + c] : 0.0;
             if (r == c) tau[r] = Ts[r * 65 + r];
-            if (r <= c) Wp[(size_t)c * ldw + r] = sgn[r] * R[(size_t)c * B + r];
+            if (r <= c) Wp[(size_t)c * ldw + r] = (T)(sgn[r] * R[(size_t)c * B + r]);
         }
     }
 }
@@ -709,11 +710,16 @@ void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st)
 {
     hipLaunchKernelGGL(k_chol_qr, dim3(1), dim3(256), 0, st, B, pass, cq, flag);
 }
-void launch_hh_rebuild(double *Vd, int m, int B, double *Wp, int ldw, double *cq, double *Tf, double *tau,
+template <typename T>
+void launch_hh_rebuild(T *Vd, int m, int B, T *Wp, int ldw, double *cq, double *Tf, double *tau,
                        const unsigned *flag, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_hh_rebuild, dim3(1), dim3(256), 0, st, Vd, m, B, Wp, ldw, cq, Tf, tau, flag);
+    hipLaunchKernelGGL(k_hh_rebuild<T>, dim3(1), dim3(256), 0, st, Vd, m, B, Wp, ldw, cq, Tf, tau, flag);
 }
+template void launch_hh_rebuild<double>(double *, int, int, double *, int, double *, double *, double *,
+                                        const unsigned *, hipStream_t);
+template void launch_hh_rebuild<float>(float *, int, int, float *, int, double *, double *, double *,
+                                       const unsigned *, hipStream_t);
 size_t cholqr_scratch_doubles() { return (size_t)6 * 64 * 64; }
 
 template hipError_t launch_panel_qr<double>(double *, int, int, int, int, int, double *, double *, double *,

@@ -22,7 +22,8 @@ constexpr int CQ_G = 0, CQ_R1 = 1, CQ_R1INV = 2, CQ_R2INV = 3, CQ_R = 4, CQ_UINV
 size_t cholqr_scratch_doubles();
 void launch_gram_reduce(const double *Gp, int np, int BB, double *G, hipStream_t st);
 void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st);
-void launch_hh_rebuild(double *Vd, int m, int B, double *Wp, int ldw, double *cq, double *Tf, double *tau,
+template <typename T>
+void launch_hh_rebuild(T *Vd, int m, int B, T *Wp, int ldw, double *cq, double *Tf, double *tau,
                        const unsigned *flag, hipStream_t st);
 int symm_splits(int m);
 int symm_kchunk(int m, int S);
