@@ -151,26 +151,31 @@ __global__ void k_lambda(const double *__restrict__ S, const double *__restrict_
     atomic_max_pos(&stat[2], fabs(l));
 }
 
-__global__ void k_stats(const double *__restrict__ S, const double *__restrict__ G, int ncx, int odd,
-                        double *__restrict__ stat)
+// Columns j = blockIdx.x, blockIdx.x + gridDim.x, ... (rows i >= j); one
+// atomic per workgroup after a reduction in LDS.
+__global__ __launch_bounds__(256) void k_stats(const double *__restrict__ S, const double *__restrict__ G, int ncx,
+                                               int odd, double *__restrict__ stat)
 {
-    const int j = blockIdx.y;
+    __shared__ double red[2][4];
     double mr = 0.0, ms = 0.0;
-    const int pj = blk_of_col(j, odd);
-    for (int i = j + blockIdx.x * 256 + threadIdx.x; i < ncx; i += gridDim.x * 256) {
-        const double r = (i == j ? 1.0 : 0.0) - G[(size_t)j * ncx + i];
-        mr = fmax(mr, fabs(r));
-        if (blk_of_col(i, odd) != pj) ms = fmax(ms, fabs(S[(size_t)j * ncx + i]));
+    for (int j = blockIdx.x; j < ncx; j += gridDim.x) {
+        const int pj = blk_of_col(j, odd);
+        for (int i = j + threadIdx.x; i < ncx; i += 256) {
+            const double r = (i == j ? 1.0 : 0.0) - G[(size_t)j * ncx + i];
+            mr = fmax(mr, fabs(r));
+            if (blk_of_col(i, odd) != pj) ms = fmax(ms, fabs(S[(size_t)j * ncx + i]));
+        }
     }
-    mr = fmax(mr, __shfl_xor(mr, 32, 64));
-    ms = fmax(ms, __shfl_xor(ms, 32, 64));
-    for (int o = 16; o > 0; o >>= 1) {
-        mr = fmax(mr, __shfl_xor(mr, o, 64));
-        ms = fmax(ms, __shfl_xor(ms, o, 64));
-    }
+    mr = wave_max(mr);
+    ms = wave_max(ms);
     if ((threadIdx.x & 63) == 0) {
-        atomic_max_pos(&stat[0], mr);
-        atomic_max_pos(&stat[1], ms);
+        red[0][threadIdx.x >> 6] = mr;
+        red[1][threadIdx.x >> 6] = ms;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomic_max_pos(&stat[0], fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3])));
+        atomic_max_pos(&stat[1], fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3])));
     }
 }
 
@@ -297,8 +302,8 @@ void launch_split_x(const double *X, int n, int nev, int odd, double *Zr, int ld
 void launch_refine_products(const double *A, int lda, int n, const double *X, int ncx, double *P, double *S,
                             double *G, hipStream_t st)
 {
-    dim3 g1(cdiv(n, 128), cdiv(ncx, 64));
-    hipLaunchKernelGGL((k_skew_mm<128, 64>), g1, dim3(256), (gemm::smem_bytes<double, 128, 64>()), st, A, lda, n,
+    dim3 g1(cdiv(n, 128), cdiv(ncx, 128));
+    hipLaunchKernelGGL((k_skew_mm<128, 128>), g1, dim3(256), (gemm::smem_bytes<double, 128, 128>()), st, A, lda, n,
                        X, ncx, P);
     const int TT = 64;
     unsigned nt = cdiv(ncx, TT);
@@ -312,8 +317,7 @@ void launch_refine_eigs(const double *S, const double *G, int ncx, int nblk, int
                         hipStream_t st)
 {
     hipLaunchKernelGGL(k_lambda, dim3(cdiv(nblk, 256)), dim3(256), 0, st, S, G, ncx, nblk, odd, lam, stat);
-    hipLaunchKernelGGL(k_stats, dim3(cdiv(ncx, 256) > 16 ? 16 : cdiv(ncx, 256), ncx), dim3(256), 0, st, S, G, ncx, odd,
-                       stat);
+    hipLaunchKernelGGL(k_stats, dim3(ncx < 1024 ? (ncx > 0 ? ncx : 1) : 1024), dim3(256), 0, st, S, G, ncx, odd, stat);
 }
 
 void launch_refine_update(const double *S, const double *G, int n, int ncx, int nblk, int odd, const double *lam,
