@@ -405,6 +405,7 @@ __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl
     // 64 (lr % 2) + lk - lr + 4ks - 16mt; inside when 0 <= lk - lr + 4ks - 16mt < 64
     const double *vb1 = Vl + (lr >> 1) * CV + (lr & 1) * 64 + lk - lr;
     const int dw = lk - lr;
+    __builtin_assume(dw >= -15 && dw <= 3);     // the tiles whose k-steps lie inside need no test
     d4 w1[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) w1[mt] = (d4){0.0, 0.0, 0.0, 0.0};
@@ -464,6 +465,7 @@ __device__ __forceinline__ void apply(Win &w, const double *Vl, const double *Tl
     // 64 (lk % 2) + lr - lk + 16rt - 4ks; inside when 0 <= lr - lk + 16rt - 4ks < 64
     const double *vb3 = Vl + (lk >> 1) * CV + (lk & 1) * 64 + lr - lk;
     const int dz = lr - lk;
+    __builtin_assume(dz >= -3 && dz <= 15);
 #pragma unroll
     for (int kc = 0; kc < 16; kc += 2) {
         double a[2][8];
