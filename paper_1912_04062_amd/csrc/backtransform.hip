@@ -650,10 +650,9 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_bt1_z(
     gemm::kloop<T, TM, TN, false, true>(fa, fb, m0, n0, 0, KK, smem, acc);
     gemm::epilogue_rmw<T, TM, TN>(
         acc, smem,
-        [=](int i, int j) -> T {
-            const int gi = m0 + i, gj = n0 + j;
-            return (gi < V.m && gj < ncols) ? Z[(size_t)gj * ldz + gi] : T(0);
-        },
+        // unconditional load at a clamped address: values outside are never
+        // stored, and a test here would become a branch around every load
+        [=](int i, int j) -> T { return Z[(size_t)min(n0 + j, ncols - 1) * ldz + min(m0 + i, V.m - 1)]; },
         [=](int i, int j, T old, T v) {
             const int gi = m0 + i, gj = n0 + j;
             if (gi < V.m && gj < ncols) Z[(size_t)gj * ldz + gi] = old - v;

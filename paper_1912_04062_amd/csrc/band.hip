@@ -372,7 +372,9 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_skew_syr2k(T *__restrict__ W,
     auto inside = [=](int i, int j) { return m0 + i < m && n0 + j < m && (!diag || i > j); };
     gemm::epilogue_rmw<T, TT, TT>(
         acc, smem,
-        [=](int i, int j) -> T { return inside(i, j) ? A0[(size_t)(n0 + j) * ldw + m0 + i] : T(0); },
+        // unconditional load at a clamped address: values outside are never
+        // stored, and a test here would become a branch around every load
+        [=](int i, int j) -> T { return A0[(size_t)min(n0 + j, m - 1) * ldw + min(m0 + i, m - 1)]; },
         [=](int i, int j, T old, T v) {
             if (inside(i, j)) A0[(size_t)(n0 + j) * ldw + m0 + i] = old + v;
         });
