@@ -219,18 +219,26 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_skew_symm(const T *__restrict
     const int s = blockIdx.y;
     const int kb = s * kchunk, ke = min(m, kb + kchunk);
     const T *A0 = W + (size_t)r0 * ldw + r0;
+    // every fetch is one unconditional load at a clamped (valid, finite)
+    // address scaled by 0 or +-1: a select here would become a branch around
+    // the load, and the chunk's loads would no longer be in flight together
+    const int mc = m - 1;
     auto f_low = [=](int i, int k) -> T {      // k < i
-        return (i < m && k < ke) ? A0[(size_t)k * ldw + i] : T(0);
+        const T x = A0[(size_t)min(k, mc) * ldw + min(i, mc)];
+        return x * T((i < m && k < ke) ? 1 : 0);
     };
     auto f_up = [=](int i, int k) -> T {       // k > i: A(i,k) = -A(k,i)
-        return (i < m && k < ke) ? -A0[(size_t)i * ldw + k] : T(0);
+        const T x = A0[(size_t)min(i, mc) * ldw + min(k, mc)];
+        return x * T((i < m && k < ke) ? -1 : 0);
     };
     auto f_mix = [=](int i, int k) -> T {
-        if (i >= m || k >= ke || i == k) return T(0);
-        return (i > k) ? A0[(size_t)k * ldw + i] : -A0[(size_t)i * ldw + k];
+        const int r = max(i, k), c = min(i, k);
+        const T x = A0[(size_t)min(c, mc) * ldw + min(r, mc)];
+        return x * T((i >= m || k >= ke || i == k) ? 0 : ((i > k) ? 1 : -1));
     };
     auto f_v = [=](int j, int k) -> T {
-        return (j < B && k < ke) ? Vd[(size_t)j * m + k] : T(0);
+        const T x = Vd[(size_t)min(j, B - 1) * m + min(k, mc)];
+        return x * T((j < B && k < ke) ? 1 : 0);
     };
     gemm::Acc<T, TM, TN> acc;
     acc.zero();

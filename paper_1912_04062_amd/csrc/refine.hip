@@ -270,10 +270,8 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_xe(const double *__restrict__
     // the old values come from X (double) and the result goes to Xn
     gemm::epilogue_rmw<T, TM, TN>(
         acc, smem,
-        [=](int i, int j) -> double {
-            const int gi = m0 + i, gj = n0 + j;
-            return (gi < n && gj < ncx) ? X[(size_t)gj * n + gi] : 0.0;
-        },
+        // unconditional load at a clamped address: values outside are never stored
+        [=](int i, int j) -> double { return X[(size_t)min(n0 + j, ncx - 1) * n + min(m0 + i, n - 1)]; },
         [=](int i, int j, double old, T v) {
             const int gi = m0 + i, gj = n0 + j;
             if (gi < n && gj < ncx) Xn[(size_t)gj * n + gi] = old + (double)v;
