@@ -364,13 +364,17 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_skew_syr2k(T *__restrict__ W,
     int I, J;
     tri_index(blockIdx.x, I, J);
     const int m0 = I * TT, n0 = J * TT;
+    // unconditional loads at clamped rows scaled by 0 or +-1 (no branch
+    // around the loads); k < 2B always
     auto fa = [=](int i, int k) -> T {
-        if (i >= m) return T(0);
-        return k < B ? Vd[(size_t)k * m + i] : Wd[(size_t)(k - B) * m + i];
+        const bool lo = k < B;
+        const T x = (lo ? Vd : Wd)[(size_t)(lo ? k : k - B) * m + min(i, m - 1)];
+        return x * T(i < m ? 1 : 0);
     };
     auto fb = [=](int j, int k) -> T {
-        if (j >= m) return T(0);
-        return k < B ? Wd[(size_t)k * m + j] : -Vd[(size_t)(k - B) * m + j];
+        const bool lo = k < B;
+        const T x = (lo ? Wd : Vd)[(size_t)(lo ? k : k - B) * m + min(j, m - 1)];
+        return x * T(j < m ? (lo ? 1 : -1) : 0);
     };
     gemm::Acc<T, TT, TT> acc;
     acc.zero();
