@@ -131,13 +131,17 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 double x0v = 0.0;
                 if (k == 0 && tid < 64 && tid < L) x0v = ld_coh(&ab[(size_t)c * ldab + (lo + tid - c)]);
                 const bool rowd = tx < L, rowb = tx < L2;
+                // every load is issued at a valid band position (clamped) and
+                // scaled by 0 or 1: a test around a load becomes a branch per
+                // load; the band storage holds finite values everywhere
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int jl = ty + 4 * q;
-                    vd[q] = 0.0;
-                    vb[q] = 0.0;
-                    if (rowd && tx > jl) vd[q] = ld_coh(&ab[(size_t)(lo + jl) * ldab + (tx - jl)]);
-                    if (rowb && jl < L) vb[q] = ld_coh(&ab[(size_t)(lo + jl) * ldab + (hi + 1 + tx - lo - jl)]);
+                    const size_t col = (size_t)min(lo + jl, n - 1) * ldab;
+                    const double xd = ld_coh(&ab[col + min(max(tx - jl, 0), 2 * b)]);
+                    const double xb = ld_coh(&ab[col + min(max(hi + 1 + tx - lo - jl, 0), 2 * b)]);
+                    vd[q] = xd * ((rowd && tx > jl) ? 1.0 : 0.0);
+                    vb[q] = xb * ((rowb && jl < L) ? 1.0 : 0.0);
                 }
                 if (k == 0 && tid < 64) reflect(x0v, L, c, lo, s, 1u);
                 // full skew block in LDS (zeros outside L x L)
