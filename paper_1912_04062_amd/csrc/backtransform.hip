@@ -18,6 +18,7 @@
 //                by the stage-1 back-transformation Z <- (I - V T V^T) Z and
 //                by the block Gram-Schmidt of the eigenvector basis.
 #include "common.h"
+#include "small64.h"
 #include "gemm.h"
 #include "kernels.h"
 
@@ -673,8 +674,9 @@ __global__ __launch_bounds__(256) void k_merge_t(const double *__restrict__ T1, 
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int o = off(tx, ty + 4 * q);
-            t1[q] = (o >= 0) ? T1[o] : 0.0;
-            t2[q] = (o >= 0) ? T2[o] : 0.0;
+            const bool up = o >= 0 && tx <= ty + 4 * q;       // T1, T2 upper, zero elsewhere
+            t1[q] = up ? T1[o] : 0.0;
+            t2[q] = up ? T2[o] : 0.0;
         }
         sum_partials_2d(Gp, S, (size_t)b * b, off, acc);
 #pragma unroll
@@ -686,28 +688,16 @@ __global__ __launch_bounds__(256) void k_merge_t(const double *__restrict__ T1, 
         }
     }
     __syncthreads();
-#pragma unroll 4
-    for (int q = 0; q < 16; ++q) {                   // M1 = G T2 (T2 upper)
-        const int v = ty + 4 * q;
-        double s = 0.0;
-        for (int w = 0; w <= v && w < b; ++w) s += G[tx * 65 + w] * A2[w * 65 + v];
-        M1[tx * 65 + v] = s;
-    }
+    mm64<false>(G, A2, M1);                          // M1 = G T2
     __syncthreads();
-#pragma unroll 4
-    for (int q = 0; q < 16; ++q) {                   // T12 = -T1 M1 (T1 upper), into G
-        const int j = ty + 4 * q;
-        double s = 0.0;
-        for (int u = tx; u < b; ++u) s += A1[tx * 65 + u] * M1[u * 65 + j];
-        G[tx * 65 + j] = -s;
-    }
+    mm64<false>(A1, M1, G);                          // T1 M1 (into G); T12 = -T1 M1
     __syncthreads();
     for (int j = ty; j < K; j += 4)
         for (int i = tx; i < K; i += 64) {
             double val = 0.0;
             if (i < b && j < b) val = A1[i * 65 + j];
             else if (i >= b && j >= b) val = A2[(i - b) * 65 + (j - b)];
-            else if (i < b) val = G[i * 65 + (j - b)];
+            else if (i < b) val = -G[i * 65 + (j - b)];
             Tm[(size_t)j * K + i] = val;
         }
 }

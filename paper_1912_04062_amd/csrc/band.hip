@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void k_small(const double *__restrict__ Gp, in
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int o = off(tx, ty + 4 * q);
-            tf[q] = (o >= 0) ? Tf[o] : 0.0;
+            tf[q] = (o >= 0 && tx <= ty + 4 * q) ? Tf[o] : 0.0;   // T upper, zero elsewhere
         }
         sum_partials_2d(Gp, nchunk, (size_t)B * B, off, acc);
 #pragma unroll
@@ -301,22 +301,16 @@ __global__ __launch_bounds__(256) void k_small(const double *__restrict__ Gp, in
         }
     }
     __syncthreads();
-#pragma unroll 4
-    for (int q = 0; q < 16; ++q) {                   // M1 = G T (T upper)
-        const int j = ty + 4 * q;
-        double s = 0.0;
-        for (int u = 0; u <= j && u < B; ++u) s += G[tx * 65 + u] * Tm[u * 65 + j];
-        M1[tx * 65 + j] = s;
-    }
+    mm64<false>(G, Tm, M1);                          // M1 = G T
     __syncthreads();
-#pragma unroll 4
-    for (int q = 0; q < 16; ++q) {                   // X = T^T M1
+    mm64<true>(Tm, M1, G);                           // X = T^T M1 (into G)
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
         if (tx < B && j < B) {
-            double s = 0.0;
-            for (int u = 0; u <= tx; ++u) s += Tm[u * 65 + tx] * M1[u * 65 + j];
             Tx[(size_t)j * 2 * B + tx] = (T)Tm[tx * 65 + j];
-            Tx[(size_t)j * 2 * B + B + tx] = (T)(-0.5 * s);
+            Tx[(size_t)j * 2 * B + B + tx] = (T)(-0.5 * G[tx * 65 + j]);
         }
     }
 }

@@ -106,4 +106,44 @@ __device__ __forceinline__ void lu_signed64(double *M, int B, double *sgn)
     __syncthreads();
 }
 
+// C = op(A) B for 64 x 64 matrices in LDS (row r at r * 65) on the FP64
+// MFMA: wavefront w computes the 32 x 32 quadrant (w / 2, w % 2); op(A) = A,
+// or A^T with TA.  C must not overlap A or B; the caller synchronizes before
+// (operands written) and after (C read by other wavefronts).
+template <bool TA>
+__device__ __forceinline__ void mm64(const double *A, const double *B, double *C)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm0 = (w >> 1) * 32, wn0 = (w & 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k4 = 0; k4 < 64; k4 += 4) {
+        const int k = k4 + lk;
+        double a[2], bb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row = wm0 + 16 * i + lr;
+            a[i] = TA ? A[k * 65 + row] : A[row * 65 + k];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bb[j] = B[k * 65 + wn0 + 16 * j + lr];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma_16x16x4(a[i], bb[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                C[(wm0 + 16 * i + mfma_row<double>(lane, r)) * 65 + wn0 + 16 * j + lr] = acc[i][j][r];
+}
+
 }  // namespace
