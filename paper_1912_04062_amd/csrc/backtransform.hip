@@ -46,10 +46,10 @@ __global__ __launch_bounds__(256) void k_bt2_tfac(const double *__restrict__ V2,
                                                   int b, int nb2, T *__restrict__ T2, T *__restrict__ V2t,
                                                   int rowmajor)
 {
-    __shared__ double Vs[64 * 65];       // Vs[r][i]
+    __shared__ double Vs[64 * 65];       // Vs[r][i]; T after the Gram matrix is formed
     __shared__ double Gm[64 * 65];       // Gram (strict upper; zero elsewhere)
-    __shared__ double Tm[64 * 65];
     __shared__ double tv[64], part[4][64];
+    double *Tm = Vs;                     // 67 KB of LDS: two workgroups per CU
     const size_t g = blockIdx.x;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const double *Vg = V2 + g * (size_t)b * nb2;
@@ -59,7 +59,6 @@ __global__ __launch_bounds__(256) void k_bt2_tfac(const double *__restrict__ V2,
         if (V2t) V2t[g * (size_t)b * nb2 + e] = (T)Vg[e];
     }
     if (tid < 64) tv[tid] = (tid < nb2) ? tau2[g * nb2 + tid] : 0.0;
-    for (int e = tid; e < 64 * 65; e += 256) Tm[e] = 0.0;
     __syncthreads();
     // Gram: v_i . v_j (i < j), overlap rows j..i+b-1 (absolute), r = row - i
     for (int e = tid; e < 64 * 64; e += 256) {
@@ -71,6 +70,8 @@ __global__ __launch_bounds__(256) void k_bt2_tfac(const double *__restrict__ V2,
         }
         Gm[i * 65 + j] = s;
     }
+    __syncthreads();
+    for (int e = tid; e < 64 * 65; e += 256) Tm[e] = 0.0;
     __syncthreads();
     // T[i][j] = -tau_j sum_{i <= u < j} T[i][u] G[u][j], T[j][j] = tau_j.  T
     // starts at zero and column u is written at step u, so the sum runs over
