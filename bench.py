@@ -133,19 +133,28 @@ def main():
     F = useful_flops(n, nev)
     forms = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
     results = {}
+    warm = max(args.warmup, 1)      # at least one untimed run (it also names the dominant kernel)
     for form in forms:
-        for _ in range(args.warmup):
-            h.solve(Ad, precision=form, out=out)
+        # untimed runs time every kernel class (the table of kernels_ms) and name
+        # the dominant kernel; the timed steps then keep HIP events only around
+        # that kernel when it is the stage-2 application (one launch), so that
+        # the timers of the many small launches stay out of the timed region
+        full = None
+        for w in range(warm):
+            h.solve(Ad, precision=form, out=out, profile=1)
+            full = h.last_info.as_dict()
         torch.cuda.synchronize()
+        kfull = {k: v["ms"] for k, v in full["kernels"].items()}
+        prof = 2 if max(kfull, key=kfull.get) == "bt2" else 1
         infos = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            h.solve(Ad, precision=form, out=out, profile=1)
+            h.solve(Ad, precision=form, out=out, profile=prof)
             infos.append(h.last_info.as_dict())
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
         acc = accuracy(Ad, *out) if args.check else None      # untimed
-        results[form] = {"wall": wall, "infos": infos, "accuracy": acc,
+        results[form] = {"wall": wall, "infos": infos, "accuracy": acc, "kernels_untimed": kfull,
                          "refine_sweeps": infos[-1]["refine_sweeps"]}
 
     def ok(form):
@@ -161,7 +170,7 @@ def main():
     # dominant kernel of the reported form: the largest average device time
     stage_avg = {k: float(np.mean([i["ms_stage"][k] for i in infos])) for k in infos[0]["ms_stage"]}
     kern = {k: float(np.mean([i["kernels"][k]["ms"] for i in infos])) for k in infos[0]["kernels"]}
-    dom = max(kern, key=kern.get)
+    dom = max(results[best]["kernels_untimed"], key=results[best]["kernels_untimed"].get)
     kinfo = infos[0]["kernels"][dom]
     dtype = "f64" if best == "fp64" else "f32+f64"
     kdtype = "f64" if (best == "fp64" or dom in ("bulge_chase", "tridiag", "refine", "panel_qr")) else "f32"
@@ -180,13 +189,13 @@ def main():
                           "skew_syr2k": "k_skew_syr2k", "refine": "refinement kernels"}.get(dom, dom)
     roof["launches_per_step"] = kinfo["launches"]
     roof["ms_per_step"] = kern[dom]
-    roof["kernels_ms"] = kern
+    roof["kernels_ms"] = results[best]["kernels_untimed"]   # from an untimed run with every kernel timed
     form_summary = {f: {"ms_per_step": r["wall"] * 1e3, "tflops": F / r["wall"] / 1e12,
                         "refine_sweeps": r["refine_sweeps"], "accuracy": r["accuracy"]}
                     for f, r in results.items()}
     line = {
         "metric": "skew-EVD time-to-solution n=16384, n/2 eigvecs: FP32+refine vs FP64, TFLOP/s",
-        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": warm,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": f"dense random skew-symmetric A=(B-B^T)/2, B iid N(0,1), seed 4, "

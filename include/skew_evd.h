@@ -59,7 +59,8 @@ typedef struct skew_evd_opts {
     double refine_tol;      /* precision form: stop when the normalised
                                residual estimate is below this (default 1e-14) */
     size_t workspace_limit; /* bytes; 0 = unlimited.  Exceeding it returns NOMEM */
-    int profile;            /* 1: time the main kernels with HIP events (info->kern) */
+    int profile;            /* 1: time the main kernels with HIP events (info->kern);
+                               2: time only the stage-2 application kernel */
     int reserved[7];
 } skew_evd_opts;
 
@@ -95,7 +96,7 @@ typedef struct skew_evd_info {
     int refine_sweeps;      /* sweeps performed (precision form) */
     double refine_residual; /* last normalised residual estimate (precision form) */
     size_t workspace_bytes; /* device workspace held by the handle */
-    skew_evd_kstat kern[SKEW_EVD_NKERN]; /* filled when opts.profile = 1 */
+    skew_evd_kstat kern[SKEW_EVD_NKERN]; /* filled when opts.profile = 1 (only SKEW_EVD_K_BT2 with 2) */
 } skew_evd_info;
 
 typedef struct skew_evd_handle_s *skew_evd_handle;

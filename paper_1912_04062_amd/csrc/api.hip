@@ -51,6 +51,7 @@ struct skew_evd_handle_s {
     unsigned *ctl_host = nullptr;   // pinned copy of the control words
     // per-kernel timing (opts.profile)
     bool prof = false;
+    int prof_only = -1;             // >= 0: time only this kernel class
     std::vector<hipEvent_t> kev;
     size_t kev_used = 0;
     struct KRec { int kid; size_t e0, e1; };
@@ -232,20 +233,21 @@ hipError_t kt_event(skew_evd_handle h, size_t *idx)
 }
 hipError_t kt_begin(skew_evd_handle h, int kid)
 {
-    if (!h->prof) return hipSuccess;
+    if (!h->prof || (h->prof_only >= 0 && kid != h->prof_only)) return hipSuccess;
     return kt_event(h, &h->kopen[kid]);
 }
 hipError_t kt_end(skew_evd_handle h, int kid)
 {
-    if (!h->prof) return hipSuccess;
+    if (!h->prof || (h->prof_only >= 0 && kid != h->prof_only)) return hipSuccess;
     size_t e1;
     hipError_t r = kt_event(h, &e1);
     h->krec.push_back({kid, h->kopen[kid], e1});
     return r;
 }
-void kt_reset(skew_evd_handle h, bool on)
+void kt_reset(skew_evd_handle h, bool on, int only = -1)
 {
     h->prof = on;
+    h->prof_only = only;
     h->kev_used = 0;
     h->krec.clear();
 }
@@ -635,7 +637,7 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     int rc = ensure_ws(h, L.total, o.workspace_limit);
     if (rc) return rc;
     hipStream_t st = h->stream;
-    kt_reset(h, o.profile != 0);
+    kt_reset(h, o.profile != 0, o.profile == 2 ? SKEW_EVD_K_BT2 : -1);
     bool rec[NSTAGE_EV] = {};
     HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, st));
     HCHK(hipEventRecord(h->ev[0], st));
