@@ -18,14 +18,15 @@
 // The reflector of step k+1 comes from column lo of that bulge.
 //
 // Pipelining: sweep s+1 may run step k once sweep s has completed step k+1
-// and has published the first entry (beta) of the pivot column of its step
-// k+2.  Step k+2 of sweep s touches exactly one entry that step k of sweep
-// s+1 also touches: that beta, in the last row of the block below the
-// diagonal block; it is known as soon as the reflector of step k+2 is formed
-// (before sweep s waits for sweep s-1), so it is published first.  Every
-// other pair of steps that touches a common entry is ordered by the
-// completion of step k+1.  The per-sweep counter progress[s] holds
-// 2*(steps completed) + 1 once the next step's beta is in memory, and
+// and has stored the first entry (beta) of the pivot column of its step k+2.
+// Step k+2 of sweep s touches exactly one entry that step k of sweep s+1
+// also touches: that beta, in the last row of the block below the diagonal
+// block.  The pivot column of step k+2 is column 0 of the block below the
+// diagonal block of step k+1, so step k+1 forms the next reflector itself
+// and stores (beta, 0, ..., 0) in place of that column together with its own
+// updates.  Every other pair of steps that touches a common entry is ordered
+// by the completion of step k+1.  The per-sweep counter progress[s] holds
+// 2*(steps completed) + 1 (the next step's beta is then in memory too), and
 // 2*nsteps + 1 when the sweep is done; a waiting step needs
 // min(2k + 5, 2 nsteps(s) + 1).  Sweeps are dealt round-robin to the
 // workgroups of a cooperative launch and every wait is bounded.
@@ -46,9 +47,9 @@ __device__ __forceinline__ int nsteps_of(int n, int b, int s) { return 1 + (n - 
 // pivot column (its column 0) and left block (columns 1..b-1), and no other
 // sweep writes it between the two steps except for the beta entry, which is
 // in place before the step's wait ends.  It therefore stays in LDS (two
-// buffers, alternating) and the next reflector is computed from it before
-// waiting on the previous sweep; only the diagonal block and the new below
-// block are loaded after the wait.
+// buffers, alternating) and the next reflector is computed from it at the
+// end of the step; only the new below block and the last row of the
+// diagonal block are loaded after the wait of the next step.
 //
 // Thread (tx, ty) = (tid % 64, tid / 64) owns row tx and columns ty + 4q
 // (q = 0..15) of the 64 x 64 blocks, so every global access of a wavefront is
@@ -59,20 +60,19 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                                                      const int *__restrict__ goff,
                                                      unsigned *progress, unsigned *err)
 {
-    __shared__ double v[64], wv[64], dots[64], y2[64];
+    __shared__ double vv[2][64], wv[64], dots[64], y2[64];
     __shared__ double pw[4][64], py[4][64], pd[4][64];
     __shared__ double dia[64 * CH_LD];
     __shared__ double bw[2][64 * CH_LD];
-    __shared__ double scal[2];
+    __shared__ double tau_s[2];
     __shared__ int abort_flag;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     if (tid == 0) abort_flag = 0;
     __syncthreads();
 
-    // Householder reflector of x (L entries, lane i holds x_i) by wavefront 0;
-    // writes v, scal and the reduced column (beta, 0, ..., 0) to the band,
-    // then publishes the beta (counter value `flag`).
-    auto reflect = [&](double xi, int L, int c, int lo, int s, unsigned flag) {
+    // Householder reflector of x (L entries, lane i of wavefront 0 holds x_i)
+    // into buffer p (v with v_0 = 1, and tau); returns beta in every lane.
+    auto reflector = [&](double xi, int L, int p) -> double {
         double sq = (tid >= 1 && tid < L) ? xi * xi : 0.0;
         sq = wave_sum(sq);
         const double x0 = __shfl(xi, 0, 64);
@@ -83,11 +83,9 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
             t = (beta - x0) / beta;
             scale = 1.0 / (x0 - beta);
         }
-        v[tid] = (tid == 0) ? 1.0 : ((tid < L) ? xi * scale : 0.0);
-        if (tid == 0) { scal[0] = t; scal[1] = beta; }
-        if (tid < L) st_coh(&ab[(size_t)c * ldab + (lo + tid - c)], (tid == 0) ? beta : 0.0);
-        wait_vmem();
-        if (tid == 0) st_relaxed(&progress[s], flag);
+        vv[p][tid] = (tid == 0) ? 1.0 : ((tid < L) ? xi * scale : 0.0);
+        if (tid == 0) tau_s[p] = t;
+        return beta;
     };
 
     for (int s = blockIdx.x; s < n - 2; s += gridDim.x) {
@@ -95,6 +93,7 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
         const int nprev = (s > 0) ? nsteps_of(n, b, s - 1) : 0;
         const int sig = s / nb2, col = s % nb2;
         int cur = 0;                              // buffer holding the previous below block
+        int vc = 0;                               // buffer holding this step's reflector
         for (int k = 0; k < nst; ++k) {
             const int lo = s + 1 + k * b;
             const int c = (k == 0) ? s : lo - b;
@@ -103,10 +102,28 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
             const int bhi = min(hi + b, n - 1);
             const int L2 = bhi - hi;
             const int nlc = lo - c - 1;           // 0 for k = 0, b - 1 otherwise
+            const bool more = k + 1 < nst;
             const double *lb = bw[cur];           // previous below block: rows R_k, cols R_{k-1}
             double *nb = bw[cur ^ 1];
-            // reflector from the carried pivot column (before the wait)
-            if (k > 0 && tid < 64) reflect((tid < L) ? lb[tid * CH_LD] : 0.0, L, c, lo, s, 2u * k + 1u);
+            const double *v = vv[vc];
+            // Diagonal block (strict lower part).  Every load is issued at a
+            // valid band position (clamped) and scaled by 0 or 1: a test
+            // around a load becomes a branch per load; the band storage holds
+            // finite values everywhere.
+            double vd[16], vb[16];
+            auto load_dia = [&]() {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = ty + 4 * q;
+                    const size_t cj = (size_t)min(lo + jl, n - 1) * ldab;
+                    vd[q] = ld_coh(&ab[cj + min(max(tx - jl, 0), 2 * b)]);
+                }
+            };
+            // For k > 0 the wait of step k - 1 ensured that the previous sweep
+            // completed its step k; after that only its step k + 1 writes the
+            // block, in the last row (left block of that step), so all other
+            // rows are loaded before the wait.
+            if (k > 0) load_dia();
             if (s > 0) {
                 if (tid == 0) {
                     const unsigned need = (unsigned)min(2 * k + 5, 2 * nprev + 1);
@@ -124,26 +141,29 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 if (abort_flag) return;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-            // diagonal block (strict lower part) and new below block, all
-            // loads issued before use
-            double vd[16], vb[16];
+            // new below block (and the rest of the diagonal block), all loads
+            // issued before use
             {
                 double x0v = 0.0;
                 if (k == 0 && tid < 64 && tid < L) x0v = ld_coh(&ab[(size_t)c * ldab + (lo + tid - c)]);
-                const bool rowd = tx < L, rowb = tx < L2;
-                // every load is issued at a valid band position (clamped) and
-                // scaled by 0 or 1: a test around a load becomes a branch per
-                // load; the band storage holds finite values everywhere
+                const bool rowb = tx < L2;
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int jl = ty + 4 * q;
-                    const size_t col = (size_t)min(lo + jl, n - 1) * ldab;
-                    const double xd = ld_coh(&ab[col + min(max(tx - jl, 0), 2 * b)]);
-                    const double xb = ld_coh(&ab[col + min(max(hi + 1 + tx - lo - jl, 0), 2 * b)]);
-                    vd[q] = xd * ((rowd && tx > jl) ? 1.0 : 0.0);
+                    const size_t cj = (size_t)min(lo + jl, n - 1) * ldab;
+                    const double xb = ld_coh(&ab[cj + min(max(hi + 1 + tx - lo - jl, 0), 2 * b)]);
                     vb[q] = xb * ((rowb && jl < L) ? 1.0 : 0.0);
                 }
-                if (k == 0 && tid < 64) reflect(x0v, L, c, lo, s, 1u);
+                if (k == 0 || tx == L - 1) load_dia();
+                // masks applied only now, so that no wait for the loads
+                // issued before the wait precedes the poll
+#pragma unroll
+                for (int q = 0; q < 16; ++q) vd[q] *= (tx < L && tx > ty + 4 * q) ? 1.0 : 0.0;
+                // the first reflector of the sweep, from column s
+                if (k == 0 && tid < 64) {
+                    const double beta = reflector(x0v, L, vc);
+                    if (tid < L) st_coh(&ab[(size_t)c * ldab + (lo + tid - c)], (tid == 0) ? beta : 0.0);
+                }
                 // full skew block in LDS (zeros outside L x L)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
@@ -157,7 +177,7 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 }
             }
             __syncthreads();
-            const double t = scal[0];
+            const double t = tau_s[vc];
             // ---- products with v: w = t A v (diagonal block), y2 = t B v
             // (below block), dots = t v^T C (left block); four partial sums
             {
@@ -179,6 +199,12 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
             else if (ty == 1) y2[tx] = t * (py[0][tx] + py[1][tx] + py[2][tx] + py[3][tx]);
             else if (ty == 2) dots[tx] = t * (pd[0][tx] + pd[1][tx] + pd[2][tx] + pd[3][tx]);
             __syncthreads();
+            // ---- reflector of step k + 1 from column 0 of the new below block
+            // (wavefront 0 holds that column: v_0 = 1); its beta and zeros
+            // replace the column in the stores below, so the step publishes
+            // them together with its own updates
+            double beta_n = 0.0;
+            if (more && ty == 0) beta_n = reflector(vb[0] - y2[tx], L2, vc ^ 1);
             // ---- updates, written back (the new below block also stays in LDS)
             {
                 const double vi = v[tx], wi = wv[tx], yi = y2[tx];
@@ -193,7 +219,8 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                         st_coh(&ab[(size_t)(lo + jl) * ldab + (tx - jl)], vd[q] + vi * wv[jl] - wi * v[jl]);
                     const double val = vb[q] - yi * v[jl];
                     nb[tx * CH_LD + jl] = val;
-                    if (tx < L2 && jl < L) st_coh(&ab[(size_t)(lo + jl) * ldab + (hi + 1 + tx - lo - jl)], val);
+                    const double out = (q == 0 && more && ty == 0) ? ((tx == 0) ? beta_n : 0.0) : val;
+                    if (tx < L2 && jl < L) st_coh(&ab[(size_t)(lo + jl) * ldab + (hi + 1 + tx - lo - jl)], out);
                 }
             }
             // ---- reflector for the back-transformation
@@ -203,8 +230,9 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 if (tid == 0) tau2[g * nb2 + col] = t;
             }
             wg_publish();
-            if (tid == 0) st_relaxed(&progress[s], (k + 1 == nst) ? 2u * nst + 1u : 2u * k + 2u);
+            if (tid == 0) st_relaxed(&progress[s], more ? 2u * k + 3u : 2u * nst + 1u);
             cur ^= 1;
+            vc ^= 1;
         }
     }
 }
