@@ -205,23 +205,46 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
             // them together with its own updates
             double beta_n = 0.0;
             if (more && ty == 0) beta_n = reflector(vb[0] - y2[tx], L2, vc ^ 1);
-            // ---- updates, written back (the new below block also stays in LDS)
-            {
-                const double vi = v[tx], wi = wv[tx], yi = y2[tx];
+            // ---- updates, written back.  The new below block stays in LDS.
+            // Its columns 1.. are the next step's left block, which that step
+            // stores, and no other sweep reads them in between (step k-1 of
+            // the next sweep reads only its column 0, step k of the next sweep
+            // waits for step k+1), so only column 0 (beta, 0, ..., 0) is
+            // stored.  Step k-1 of the next sweep reads the left block and
+            // column 0 of the diagonal block: they are stored before the
+            // publish, the rest of the diagonal block after it (the publish of
+            // step k+1 waits for every earlier store; the last step of a
+            // sweep stores everything before its publish).
+            const double vi = v[tx], wi = wv[tx], yi = y2[tx];
+            auto store_dia = [&](int q) {
+                const int jl = ty + 4 * q;
+                if (tx < L && tx > jl)
+                    st_coh(&ab[(size_t)(lo + jl) * ldab + (tx - jl)], vd[q] + vi * wv[jl] - wi * v[jl]);
+            };
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int jl = ty + 4 * q;
-                    if (tx < L && jl < nlc) {
-                        const int j = c + 1 + jl;
-                        st_coh(&ab[(size_t)j * ldab + (lo + tx - j)], lb[tx * CH_LD + 1 + jl] - vi * dots[jl]);
-                    }
-                    if (tx < L && tx > jl)
-                        st_coh(&ab[(size_t)(lo + jl) * ldab + (tx - jl)], vd[q] + vi * wv[jl] - wi * v[jl]);
-                    const double val = vb[q] - yi * v[jl];
-                    nb[tx * CH_LD + jl] = val;
-                    const double out = (q == 0 && more && ty == 0) ? ((tx == 0) ? beta_n : 0.0) : val;
-                    if (tx < L2 && jl < L) st_coh(&ab[(size_t)(lo + jl) * ldab + (hi + 1 + tx - lo - jl)], out);
+            for (int q = 0; q < 16; ++q) {
+                const int jl = ty + 4 * q;
+                if (tx < L && jl < nlc) {
+                    const int j = c + 1 + jl;
+                    st_coh(&ab[(size_t)j * ldab + (lo + tx - j)], lb[tx * CH_LD + 1 + jl] - vi * dots[jl]);
                 }
+                const double val = vb[q] - yi * v[jl];
+                nb[tx * CH_LD + jl] = val;
+                if (q == 0 && ty == 0 && tx < L2)
+                    st_coh(&ab[(size_t)lo * ldab + (hi + 1 + tx - lo)], more ? ((tx == 0) ? beta_n : 0.0) : val);
+            }
+            if (ty == 0) store_dia(0);
+            if (!more) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (q > 0 || ty > 0) store_dia(q);
+            }
+            wg_publish();
+            if (tid == 0) st_relaxed(&progress[s], more ? 2u * k + 3u : 2u * nst + 1u);
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (q > 0 || ty > 0) store_dia(q);
             }
             // ---- reflector for the back-transformation
             {
@@ -229,8 +252,6 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                 if (tid < b) V2[(g * nb2 + col) * b + tid] = (tid < L) ? v[tid] : 0.0;
                 if (tid == 0) tau2[g * nb2 + col] = t;
             }
-            wg_publish();
-            if (tid == 0) st_relaxed(&progress[s], more ? 2u * k + 3u : 2u * nst + 1u);
             cur ^= 1;
             vc ^= 1;
         }
