@@ -63,6 +63,7 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
     __shared__ double vv[2][64], wv[64], dots[64], y2[64];
     __shared__ double pw[4][64], py[4][64], pd[4][64];
     __shared__ double dia[64 * CH_LD];
+    __shared__ double junk[64];
     __shared__ double bw[2][64 * CH_LD];
     __shared__ double tau_s[2];
     __shared__ int abort_flag;
@@ -119,10 +120,24 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                     vd[q] = ld_coh(&ab[cj + min(max(tx - jl, 0), 2 * b)]);
                 }
             };
+            // full skew block in LDS from vd (zeros outside L x L); the lanes
+            // with nothing to write store to junk instead of branching
+            auto write_dia = [&]() {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int jl = ty + 4 * q;
+                    const double d = (tx < L && tx > jl) ? vd[q] : 0.0;
+                    double *p1 = (tx >= jl) ? &dia[tx * CH_LD + jl] : &junk[tx];
+                    double *p2 = (tx > jl) ? &dia[jl * CH_LD + tx] : &junk[tx];
+                    *p1 = d;
+                    *p2 = -d;
+                }
+            };
             // For k > 0 the wait of step k - 1 ensured that the previous sweep
             // completed its step k; after that only its step k + 1 writes the
             // block, in the last row (left block of that step), so all other
-            // rows are loaded before the wait.
+            // rows are loaded, and put into LDS, before the wait.  The loads
+            // are issued before the poll and consumed after it.
             if (k > 0) load_dia();
             if (s > 0) {
                 if (tid == 0) {
@@ -137,12 +152,17 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                         }
                     }
                 }
+                if (k > 0) write_dia();
                 __syncthreads();
                 if (abort_flag) return;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            } else if (k > 0) {
+                write_dia();
             }
-            // new below block (and the rest of the diagonal block), all loads
-            // issued before use
+            // new below block and the last row of the diagonal block (lane j
+            // of wavefront 0 holds its entry j; for k = 0 the whole block),
+            // all loads issued before use
+            double xr = 0.0;
             {
                 double x0v = 0.0;
                 if (k == 0 && tid < 64 && tid < L) x0v = ld_coh(&ab[(size_t)c * ldab + (lo + tid - c)]);
@@ -154,26 +174,22 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                     const double xb = ld_coh(&ab[cj + min(max(hi + 1 + tx - lo - jl, 0), 2 * b)]);
                     vb[q] = xb * ((rowb && jl < L) ? 1.0 : 0.0);
                 }
-                if (k == 0 || tx == L - 1) load_dia();
-                // masks applied only now, so that no wait for the loads
-                // issued before the wait precedes the poll
-#pragma unroll
-                for (int q = 0; q < 16; ++q) vd[q] *= (tx < L && tx > ty + 4 * q) ? 1.0 : 0.0;
+                if (ty == 0) {
+                    const double x = ld_coh(&ab[(size_t)min(lo + tx, n - 1) * ldab + max(L - 1 - tx, 0)]);
+                    xr = x * ((tx < L - 1) ? 1.0 : 0.0);
+                }
+                if (k == 0) {
+                    load_dia();
+                    write_dia();
+                }
                 // the first reflector of the sweep, from column s
                 if (k == 0 && tid < 64) {
                     const double beta = reflector(x0v, L, vc);
                     if (tid < L) st_coh(&ab[(size_t)c * ldab + (lo + tid - c)], (tid == 0) ? beta : 0.0);
                 }
-                // full skew block in LDS (zeros outside L x L)
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int jl = ty + 4 * q;
-                    if (tx > jl) {
-                        dia[tx * CH_LD + jl] = vd[q];
-                        dia[jl * CH_LD + tx] = -vd[q];
-                    } else if (tx == jl) {
-                        dia[tx * CH_LD + tx] = 0.0;
-                    }
+                if (ty == 0 && tx < L - 1) {
+                    dia[(L - 1) * CH_LD + tx] = xr;
+                    dia[tx * CH_LD + L - 1] = -xr;
                 }
             }
             __syncthreads();
@@ -199,12 +215,6 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
             else if (ty == 1) y2[tx] = t * (py[0][tx] + py[1][tx] + py[2][tx] + py[3][tx]);
             else if (ty == 2) dots[tx] = t * (pd[0][tx] + pd[1][tx] + pd[2][tx] + pd[3][tx]);
             __syncthreads();
-            // ---- reflector of step k + 1 from column 0 of the new below block
-            // (wavefront 0 holds that column: v_0 = 1); its beta and zeros
-            // replace the column in the stores below, so the step publishes
-            // them together with its own updates
-            double beta_n = 0.0;
-            if (more && ty == 0) beta_n = reflector(vb[0] - y2[tx], L2, vc ^ 1);
             // ---- updates, written back.  The new below block stays in LDS.
             // Its columns 1.. are the next step's left block, which that step
             // stores, and no other sweep reads them in between (step k-1 of
@@ -216,10 +226,16 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
             // step k+1 waits for every earlier store; the last step of a
             // sweep stores everything before its publish).
             const double vi = v[tx], wi = wv[tx], yi = y2[tx];
+            // (row L-1 of the diagonal block is held by wavefront 0, entry j
+            // in lane j: xr)
             auto store_dia = [&](int q) {
                 const int jl = ty + 4 * q;
-                if (tx < L && tx > jl)
+                if (tx < L - 1 && tx > jl)
                     st_coh(&ab[(size_t)(lo + jl) * ldab + (tx - jl)], vd[q] + vi * wv[jl] - wi * v[jl]);
+            };
+            auto store_last_row = [&](bool first) {
+                if (ty == 0 && tx < L - 1 && (tx == 0) == first)
+                    st_coh(&ab[(size_t)(lo + tx) * ldab + (L - 1 - tx)], xr + v[L - 1] * wi - wv[L - 1] * vi);
             };
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -228,16 +244,24 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
                     const int j = c + 1 + jl;
                     st_coh(&ab[(size_t)j * ldab + (lo + tx - j)], lb[tx * CH_LD + 1 + jl] - vi * dots[jl]);
                 }
-                const double val = vb[q] - yi * v[jl];
-                nb[tx * CH_LD + jl] = val;
-                if (q == 0 && ty == 0 && tx < L2)
-                    st_coh(&ab[(size_t)lo * ldab + (hi + 1 + tx - lo)], more ? ((tx == 0) ? beta_n : 0.0) : val);
+                nb[tx * CH_LD + jl] = vb[q] - yi * v[jl];
             }
             if (ty == 0) store_dia(0);
+            store_last_row(true);
+            // ---- reflector of step k + 1 from column 0 of the new below block
+            // (wavefront 0 holds that column: v_0 = 1), formed while the
+            // stores above are in flight; its beta and zeros are stored in
+            // place of the column, so the step publishes them with its own
+            // updates
+            if (more && ty == 0) {
+                const double beta_n = reflector(vb[0] - yi, L2, vc ^ 1);
+                if (tx < L2) st_coh(&ab[(size_t)lo * ldab + (hi + 1 + tx - lo)], (tx == 0) ? beta_n : 0.0);
+            }
             if (!more) {
 #pragma unroll
                 for (int q = 0; q < 16; ++q)
                     if (q > 0 || ty > 0) store_dia(q);
+                store_last_row(false);
             }
             wg_publish();
             if (tid == 0) st_relaxed(&progress[s], more ? 2u * k + 3u : 2u * nst + 1u);
@@ -245,6 +269,7 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
 #pragma unroll
                 for (int q = 0; q < 16; ++q)
                     if (q > 0 || ty > 0) store_dia(q);
+                store_last_row(false);
             }
             // ---- reflector for the back-transformation
             {
