@@ -80,12 +80,12 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int tn_parts_max() { return 32; }
 
-// Row splits of the Gram products of the Cholesky-QR panel path: about 256
-// rows per workgroup, at most cholqr_max_splits().
-int cholqr_max_splits() { return 64; }
+// Row splits of the Gram products of the Cholesky-QR panel path: about 128
+// rows per workgroup (a short chain of K-chunks), at most cholqr_max_splits().
+int cholqr_max_splits() { return 128; }
 int cholqr_splits(int m)
 {
-    int S = (m + 255) / 256;
+    int S = (m + 127) / 128;
     return S < 1 ? 1 : (S > cholqr_max_splits() ? cholqr_max_splits() : S);
 }
 

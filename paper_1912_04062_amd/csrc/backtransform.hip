@@ -745,15 +745,22 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_gemm_nn(const T *__restrict__
     gemm::Acc<T, TM, TN> acc;
     acc.zero();
     gemm::kloop<T, TM, TN, false, true>(fa, fb, m0, n0, 0, K, smem, acc);
-    gemm::epilogue_rmw<T, TM, TN>(
-        acc, smem,
-        // unconditional load at a clamped address (see k_bt1_z); C's old value
-        // is used only with beta
-        [=](int i, int j) -> T { return C[(size_t)min(n0 + j, N - 1) * ldc + min(m0 + i, M - 1)]; },
-        [=](int i, int j, T old, T v) {
+    if (beta) {
+        gemm::epilogue_rmw<T, TM, TN>(
+            acc, smem,
+            // unconditional load at a clamped address (see k_bt1_z)
+            [=](int i, int j) -> T { return C[(size_t)min(n0 + j, N - 1) * ldc + min(m0 + i, M - 1)]; },
+            [=](int i, int j, T old, T v) {
+                const int gi = m0 + i, gj = n0 + j;
+                if (gi < M && gj < N) C[(size_t)gj * ldc + gi] = (T)((double)old + alpha * (double)v);
+            });
+    } else {
+        // C's old value is not needed: no read round trip
+        gemm::epilogue<T, TM, TN>(acc, smem, [=](int i, int j, T v) {
             const int gi = m0 + i, gj = n0 + j;
-            if (gi < M && gj < N) C[(size_t)gj * ldc + gi] = (T)((beta ? (double)old : 0.0) + alpha * (double)v);
+            if (gi < M && gj < N) C[(size_t)gj * ldc + gi] = (T)(alpha * (double)v);
         });
+    }
 }
 
 // out = S0 * sum_s Cpart[s]  (S0: M x M column-major, M <= 64) or, with
