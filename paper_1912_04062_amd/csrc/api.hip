@@ -60,6 +60,10 @@ struct skew_evd_handle_s {
     int refine_passes = 0;
     int *goff_host = nullptr;       // pinned group offsets of the bulge-chase reflectors
     size_t goff_cap = 0;
+    // second stream: the T factors of the stage-2 groups run on it beside
+    // the tridiagonal solve
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_ev[2] = {};
     // batched form: sub-handles, each with its own stream and workspace
     std::vector<skew_evd_handle> sub;
     std::vector<hipStream_t> sub_streams;
@@ -421,13 +425,22 @@ int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, 
     return SKEW_EVD_OK;
 }
 
+int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L);
+
+// early_t: start the T factors of the stage-2 groups on the second stream
+// once the bisection (which fills the device) is queued, so that they run
+// beside the inverse iteration.
 int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const double *alpha, int nev, double *lam,
-                  double *Q, int ldq)
+                  double *Q, int ldq, bool early_t = false)
 {
     hipStream_t st = h->stream;
     const int n = p.n;
     HCHK(kt_begin(h, SKEW_EVD_K_TRIDIAG));
     skew::launch_tridiag_eigvals(alpha, n, n / 2, nev, ptr<double>(h, L.a2), ptr<double>(h, L.stats), lam, st);
+    if (early_t) {
+        int rc = start_bt2_factors(h, p, L);
+        if (rc) return rc;
+    }
     skew::launch_tridiag_eigvecs(alpha, n, nev, lam, ptr<double>(h, L.stats), ptr<double>(h, L.U0),
                                  ptr<double>(h, L.U1), ptr<double>(h, L.U2), ptr<double>(h, L.Lm),
                                  ptr<unsigned char>(h, L.Sw), ptr<double>(h, L.Yiv), ptr<double>(h, L.ivfac), Q,
@@ -440,12 +453,48 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
     return SKEW_EVD_OK;
 }
 
+// T factors of the stage-2 groups (they depend on the bulge chase only).
 template <typename T>
-int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L)
+void launch_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L, hipStream_t st)
+{
+    const int n = p.n, nev = p.nev, b = p.b;
+    if (p.prec && b == 64 && p.nb2 == 64)
+        skew::launch_bt2<double>(ptr<double>(h, L.rX), n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2),
+                                 ptr<double>(h, L.tau2), ptr<double>(h, L.T2), nullptr, ptr<int>(h, L.goff), p.nsig,
+                                 p.ngroups, 1, st);
+    else
+        skew::launch_bt2<T>(ptr<T>(h, L.Z), n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2),
+                            ptr<T>(h, L.T2), p.prec ? ptr<T>(h, L.V2t) : nullptr, ptr<int>(h, L.goff), p.nsig,
+                            p.ngroups, 1, st);
+}
+
+// Above this order the T factors run on the second stream, beside the
+// inverse iteration of the tridiagonal solve (which occupies few CUs).
+constexpr int EARLY_TFAC_MIN_N = 4096;
+
+int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L)
+{
+    if (!h->aux) {
+        HCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+        for (int i = 0; i < 2; ++i) HCHK(hipEventCreateWithFlags(&h->aux_ev[i], hipEventDisableTiming));
+    }
+    HCHK(hipEventRecord(h->aux_ev[0], h->stream));
+    HCHK(hipStreamWaitEvent(h->aux, h->aux_ev[0], 0));
+    if (p.prec) launch_bt2_factors<float>(h, p, L, h->aux);
+    else launch_bt2_factors<double>(h, p, L, h->aux);
+    HCHK(hipGetLastError());
+    HCHK(hipEventRecord(h->aux_ev[1], h->aux));
+    return SKEW_EVD_OK;
+}
+
+// early_t: the T factors were started on the second stream after the chase.
+template <typename T>
+int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L, bool early_t)
 {
     hipStream_t st = h->stream;
     const int n = p.n, nev = p.nev, b = p.b;
     T *Z = ptr<T>(h, L.Z);
+    if (early_t) HCHK(hipStreamWaitEvent(st, h->aux_ev[1], 0));
     // the BT2 timer brackets the application kernel only (D scaling and the
     // T factors of the groups come before it)
     if (p.prec && b == 64 && p.nb2 == 64) {
@@ -453,8 +502,7 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L)
         // the refinement's X buffer, unused until then) and round once
         double *Zd = ptr<double>(h, L.rX);
         skew::launch_dscale<double>(ptr<double>(h, L.Qd), n, n, nev, Zd, n, st);
-        skew::launch_bt2<double>(Zd, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2),
-                                 ptr<double>(h, L.T2), nullptr, ptr<int>(h, L.goff), p.nsig, p.ngroups, 1, st);
+        if (!early_t) launch_bt2_factors<T>(h, p, L, st);
         HCHK(kt_begin(h, SKEW_EVD_K_BT2));
         skew::launch_bt2<double>(Zd, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2),
                                  ptr<double>(h, L.T2), nullptr, ptr<int>(h, L.goff), p.nsig, p.ngroups, 2, st);
@@ -463,8 +511,7 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L)
     } else {
         T *V2t = p.prec ? ptr<T>(h, L.V2t) : nullptr;
         skew::launch_dscale<T>(ptr<double>(h, L.Qd), n, n, nev, Z, n, st);
-        skew::launch_bt2<T>(Z, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2), ptr<T>(h, L.T2),
-                            V2t, ptr<int>(h, L.goff), p.nsig, p.ngroups, 1, st);
+        if (!early_t) launch_bt2_factors<T>(h, p, L, st);
         HCHK(kt_begin(h, SKEW_EVD_K_BT2));
         skew::launch_bt2<T>(Z, n, n, 2 * nev, b, p.nb2, ptr<double>(h, L.V2), ptr<double>(h, L.tau2), ptr<T>(h, L.T2),
                             V2t, ptr<int>(h, L.goff), p.nsig, p.ngroups, 2, st);
@@ -639,6 +686,8 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     hipStream_t st = h->stream;
     kt_reset(h, o.profile != 0, o.profile == 2 ? SKEW_EVD_K_BT2 : -1);
     bool rec[NSTAGE_EV] = {};
+    // work left on the second stream by an earlier call that returned early
+    if (h->aux) HCHK(hipStreamWaitEvent(st, h->aux_ev[1], 0));
     HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, st));
     HCHK(hipEventRecord(h->ev[0], st));
     rec[0] = true;
@@ -648,10 +697,12 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     rc = stage_chase(h, p, L);
     if (rc) return rc;
     rec[3] = true;
-    rc = stage_tridiag(h, p, L, ptr<double>(h, L.alpha), nev, ptr<double>(h, L.lam), ptr<double>(h, L.Qd), n);
+    const bool early_t = n >= EARLY_TFAC_MIN_N && p.ngroups > 0;
+    rc = stage_tridiag(h, p, L, ptr<double>(h, L.alpha), nev, ptr<double>(h, L.lam), ptr<double>(h, L.Qd), n,
+                       early_t);
     if (rc) return rc;
     rec[4] = true;
-    rc = prec ? stage_backtransform<float>(h, p, L) : stage_backtransform<double>(h, p, L);
+    rc = prec ? stage_backtransform<float>(h, p, L, early_t) : stage_backtransform<double>(h, p, L, early_t);
     if (rc) return rc;
     rec[5] = rec[6] = true;
     int rsweeps = 0, refine_rc = SKEW_EVD_OK;
@@ -755,6 +806,12 @@ int skew_evd_destroy(skew_evd_handle h)
     if (h->ctl_host) (void)hipHostFree(h->ctl_host);
     if (h->goff_host) (void)hipHostFree(h->goff_host);
     for (auto e : h->kev) (void)hipEventDestroy(e);
+    if (h->aux) {
+        (void)hipStreamSynchronize(h->aux);
+        (void)hipStreamDestroy(h->aux);
+    }
+    for (auto e : h->aux_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto sh : h->sub) skew_evd_destroy(sh);
     for (auto s2 : h->sub_streams) (void)hipStreamDestroy(s2);
     delete h;
