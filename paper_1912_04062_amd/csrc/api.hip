@@ -63,7 +63,7 @@ struct skew_evd_handle_s {
     // second stream: the T factors of the stage-2 groups run on it beside
     // the tridiagonal solve
     hipStream_t aux = nullptr;
-    hipEvent_t aux_ev[2] = {};
+    hipEvent_t aux_ev[3] = {};
     // batched form: sub-handles, each with its own stream and workspace
     std::vector<skew_evd_handle> sub;
     std::vector<hipStream_t> sub_streams;
@@ -468,6 +468,28 @@ void launch_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L, hipSt
                             p.ngroups, 1, st);
 }
 
+// Stage 1 is back-transformed in merged pairs of panels for these widths.
+bool merged_bt1(const Plan &p) { return p.b == 64 || p.b == 32; }
+
+// Merged T of each pair of panels (j0, j0 + 1), j0 = P-2, P-4, ...:
+// Tm[q] = [[T_j0, -T_j0 G T_j0+1], [0, T_j0+1]], G = V_j0(b:, :)^T V_j0+1,
+// with the Gram partials in Gp.
+template <typename T>
+void launch_bt1_merges(skew_evd_handle h, const Plan &p, const Layout &L, double *Gp, hipStream_t st)
+{
+    const int n = p.n, b = p.b, P = p.npanels;
+    int q = 0;
+    for (int j0 = P - 2; j0 >= 0; j0 -= 2, ++q) {
+        const int m0 = n - (j0 + 1) * b, m1 = m0 - b;
+        const T *V0 = ptr<T>(h, L.Vall) + L.Voff[j0];
+        const T *V1 = ptr<T>(h, L.Vall) + L.Voff[j0 + 1];
+        int S = skew::launch_gemm_tn_part<T>(V0 + b, m0, V1, m1, b, b, m1, Gp, st);
+        skew::launch_merge_t(ptr<double>(h, L.Tall) + (size_t)j0 * b * b,
+                             ptr<double>(h, L.Tall) + (size_t)(j0 + 1) * b * b, Gp, S, b,
+                             ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, st);
+    }
+}
+
 // Above this order the T factors run on the second stream, beside the
 // inverse iteration of the tridiagonal solve (which occupies few CUs).
 constexpr int EARLY_TFAC_MIN_N = 4096;
@@ -476,7 +498,7 @@ int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L)
 {
     if (!h->aux) {
         HCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-        for (int i = 0; i < 2; ++i) HCHK(hipEventCreateWithFlags(&h->aux_ev[i], hipEventDisableTiming));
+        for (int i = 0; i < 3; ++i) HCHK(hipEventCreateWithFlags(&h->aux_ev[i], hipEventDisableTiming));
     }
     HCHK(hipEventRecord(h->aux_ev[0], h->stream));
     HCHK(hipStreamWaitEvent(h->aux, h->aux_ev[0], 0));
@@ -484,6 +506,14 @@ int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L)
     else launch_bt2_factors<double>(h, p, L, h->aux);
     HCHK(hipGetLastError());
     HCHK(hipEventRecord(h->aux_ev[1], h->aux));
+    // then the merged T of the stage-1 panel pairs (stage 1 only), with their
+    // Gram partials in the panel path's buffer (free after stage 1)
+    if (merged_bt1(p)) {
+        if (p.prec) launch_bt1_merges<float>(h, p, L, ptr<double>(h, L.cqGp), h->aux);
+        else launch_bt1_merges<double>(h, p, L, ptr<double>(h, L.cqGp), h->aux);
+        HCHK(hipGetLastError());
+    }
+    HCHK(hipEventRecord(h->aux_ev[2], h->aux));
     return SKEW_EVD_OK;
 }
 
@@ -519,20 +549,18 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L, bool 
     }
     HCHK(hipGetLastError());
     HCHK(hipEventRecord(h->ev[5], st));
-    if (b == 64 || b == 32) {
+    if (merged_bt1(p)) {
         // consecutive panels merged in pairs: Q_j Q_{j+1} = I - V T V^T with
         // V = [V_j, V_{j+1} shifted by b rows]; pairs end at the last panel
         const int P = p.npanels;
+        if (early_t) HCHK(hipStreamWaitEvent(st, h->aux_ev[2], 0));   // merged T factors ready
+        else launch_bt1_merges<T>(h, p, L, ptr<double>(h, L.cqGp), st);
         HCHK(kt_begin(h, SKEW_EVD_K_BT1));
         int q = 0;
         for (int j0 = P - 2; j0 >= 0; j0 -= 2, ++q) {
             const int m0 = n - (j0 + 1) * b, m1 = m0 - b;
             const T *V0 = ptr<T>(h, L.Vall) + L.Voff[j0];
             const T *V1 = ptr<T>(h, L.Vall) + L.Voff[j0 + 1];
-            int S = skew::launch_gemm_tn_part<T>(V0 + b, m0, V1, m1, b, b, m1, ptr<double>(h, L.Wp), st);
-            skew::launch_merge_t(ptr<double>(h, L.Tall) + (size_t)j0 * b * b,
-                                 ptr<double>(h, L.Tall) + (size_t)(j0 + 1) * b * b, ptr<double>(h, L.Wp), S, b,
-                                 ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, st);
             skew::launch_bt1_block<T>(Z, n, (j0 + 1) * b, m0, 2 * nev, V0, b, V1, m1,
                                       ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, 2 * b, ptr<double>(h, L.Wp),
                                       ptr<T>(h, L.Wt2), st);
@@ -687,7 +715,7 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     kt_reset(h, o.profile != 0, o.profile == 2 ? SKEW_EVD_K_BT2 : -1);
     bool rec[NSTAGE_EV] = {};
     // work left on the second stream by an earlier call that returned early
-    if (h->aux) HCHK(hipStreamWaitEvent(st, h->aux_ev[1], 0));
+    if (h->aux) HCHK(hipStreamWaitEvent(st, h->aux_ev[2], 0));
     HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, st));
     HCHK(hipEventRecord(h->ev[0], st));
     rec[0] = true;
