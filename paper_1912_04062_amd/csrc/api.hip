@@ -172,7 +172,7 @@ Layout plan_layout(const Plan &p)
 }
 
 // control words
-enum { CTL_FLAGS = 0, CTL_ERR = 1, CTL_BAR = 2, CTL_QRFLAG = 3, CTL_PROGRESS = 64 };
+enum { CTL_FLAGS = 0, CTL_ERR = 1, CTL_BAR = 2, CTL_QRFLAG = 3, CTL_HHHAND = 4, CTL_PROGRESS = 64 };
 
 int auto_band(int n)
 {
@@ -344,7 +344,7 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
             skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
             skew::launch_chol_qr(b, 2, cq, qf, st);
             skew::launch_gemm_nn<T>(Vq, m, cq + skew::CQ_R2INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
-            skew::launch_hh_rebuild<T>(Vq, m, b, P, n, cq, Tf, tauj, qf, st);
+            skew::launch_hh_rebuild<T>(Vq, m, b, P, n, cq, Tf, tauj, qf, ctl + CTL_HHHAND, ctl + CTL_ERR, st);
             if (m > b)
                 skew::launch_gemm_nn<T>(Vq + b, m, cq + skew::CQ_UINV * BB, 1, m - b, b, b, Vq + b, m, 1.0, 0, st);
             skip = qf;

@@ -539,11 +539,18 @@ __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__rest
 // Householder reconstruction from the orthonormal Q (in Vd, m x B, ld m):
 // writes V's top block L into Vd, T into Tf (column-major), tau = diag(T),
 // R_h = S R into the panel's top block of W (upper triangle), U^{-1} into
-// cq[CQ_UINV].  Nothing is done when the flag is set.
+// cq[CQ_UINV].  Nothing is done when the flag is set.  Two workgroups: both
+// factor the top block (the same deterministic steps, so the same L, U and
+// S), then workgroup 0 inverts U and writes L, U^{-1} and R_h while
+// workgroup 1 forms T and tau.  L overwrites the input block, so workgroup 1
+// sets *hand once it holds its copy of the input and workgroup 0 waits for
+// that (bounded; code 4 in *err) before writing, then clears *hand for the
+// next launch.
 template <typename T>
 __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, int B, T *__restrict__ Wp,
                                                     int ldw, double *__restrict__ cq, double *__restrict__ Tf,
-                                                    double *__restrict__ tau, const unsigned *__restrict__ flag)
+                                                    double *__restrict__ tau, const unsigned *__restrict__ flag,
+                                                    unsigned *hand, unsigned *err)
 {
     __shared__ double M[64 * 65], X[64 * 65], Ts[64 * 65], sgn[64], part[4][64], rinv[64];
     __shared__ int bad;
@@ -558,8 +565,35 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, i
     }
     if (tid < 64) sgn[tid] = 0.0;
     __syncthreads();
+    if (blockIdx.x == 1 && tid == 0) st_relaxed(hand, 1u);   // the input is in LDS
     lu_signed64(M, B, sgn);
-    tri_inv_upper(M, X, B, part, rinv);            // X = U^{-1}
+    const double *R = cq + CQ_R * BB;
+    if (blockIdx.x == 0) {
+        tri_inv_upper(M, X, B, part, rinv);        // X = U^{-1}
+        if (tid == 0) {
+            unsigned spins = 0;
+            while (ld_relaxed(hand) == 0u) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > SKEW_SPIN_LIMIT) {
+                    atomicOr(err, 4u);
+                    break;
+                }
+            }
+            st_relaxed(hand, 0u);
+        }
+        __syncthreads();
+        double *Ui = cq + CQ_UINV * BB;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = ty + 4 * q, r = tx;
+            if (r < B && c < B) {
+                Vd[(size_t)c * m + r] = (T)((r > c) ? M[r * 65 + c] : ((r == c) ? 1.0 : 0.0));
+                Ui[(size_t)c * B + r] = (r <= c) ? X[r * 65 + c] : 0.0;
+                if (r <= c) Wp[(size_t)c * ldw + r] = (T)(sgn[r] * R[(size_t)c * B + r]);
+            }
+        }
+        return;
+    }
     // T = -U S L^{-T} by columns: T[r][c] = -u_rc s_c - sum_{r <= k < c} T[r][k] l_ck
     for (int c = 0; c < B; ++c) {
         // Ts is zero below the diagonal and in columns >= c: no masks
@@ -576,18 +610,13 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, i
             Ts[tx * 65 + c] = -M[tx * 65 + c] * sgn[c] - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx]);
         __syncthreads();
     }
-    // outputs: V top block (unit lower), T, tau, U^{-1}, R_h = S R (upper triangle of the top block)
-    const double *R = cq + CQ_R * BB;
-    double *Ui = cq + CQ_UINV * BB;
+    // outputs of workgroup 1: T, tau
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int c = ty + 4 * q, r = tx;
         if (r < B && c < B) {
-            Vd[(size_t)c * m + r] = (T)((r > c) ? M[r * 65 + c] : ((r == c) ? 1.0 : 0.0));
-            Ui[(size_t)c * B + r] = (r <= c) ? X[r * 65 + c] : 0.0;
             Tf[(size_t)c * B + r] = (r <= c) ? Ts[r * 65 + c] : 0.0;
             if (r == c) tau[r] = Ts[r * 65 + r];
-            if (r <= c) Wp[(size_t)c * ldw + r] = (T)(sgn[r] * R[(size_t)c * B + r]);
         }
     }
 }
@@ -720,14 +749,14 @@ void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st)
 }
 template <typename T>
 void launch_hh_rebuild(T *Vd, int m, int B, T *Wp, int ldw, double *cq, double *Tf, double *tau,
-                       const unsigned *flag, hipStream_t st)
+                       const unsigned *flag, unsigned *hand, unsigned *err, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_hh_rebuild<T>, dim3(1), dim3(256), 0, st, Vd, m, B, Wp, ldw, cq, Tf, tau, flag);
+    hipLaunchKernelGGL(k_hh_rebuild<T>, dim3(2), dim3(256), 0, st, Vd, m, B, Wp, ldw, cq, Tf, tau, flag, hand, err);
 }
 template void launch_hh_rebuild<double>(double *, int, int, double *, int, double *, double *, double *,
-                                        const unsigned *, hipStream_t);
+                                        const unsigned *, unsigned *, unsigned *, hipStream_t);
 template void launch_hh_rebuild<float>(float *, int, int, float *, int, double *, double *, double *,
-                                       const unsigned *, hipStream_t);
+                                       const unsigned *, unsigned *, unsigned *, hipStream_t);
 size_t cholqr_scratch_doubles() { return (size_t)6 * 64 * 64; }
 
 template hipError_t launch_panel_qr<double>(double *, int, int, int, int, int, double *, double *, double *,
