@@ -54,14 +54,18 @@ typedef struct skew_evd_opts {
     int precision;          /* SKEW_EVD_PREC_*; default FP64 */
     int band;               /* semi-bandwidth b of the intermediate band matrix
                                (= panel width of the full-to-band stage); 0 = auto.
-                               Supported: 8..64, multiple of 8 */
+                               Supported: 8, 16, 32, 64 */
     int max_refine_sweeps;  /* precision form: refinement sweeps (default 2) */
     double refine_tol;      /* precision form: stop when the normalised
                                residual estimate is below this (default 1e-14) */
     size_t workspace_limit; /* bytes; 0 = unlimited.  Exceeding it returns NOMEM */
     int profile;            /* 1: time the main kernels with HIP events (info->kern);
                                2: time only the stage-2 application kernel */
-    int reserved[7];
+    int autotune;           /* 1: with band = 0 and n <= SKEW_EVD_TUNE_NMAX, take the
+                               band width skew_evd_autotune picks for n's size class
+                               (tuned on first use, cached in the handle); 0 (default):
+                               a fixed rule by n */
+    int reserved[6];
 } skew_evd_opts;
 
 /* Main kernels, for the per-kernel statistics of skew_evd_info. */
@@ -170,6 +174,25 @@ int skew_evd_tridiagonalize(skew_evd_handle h, int n, const double *A, int lda,
  * Errors: -2 n, -3 alpha, -4 nev, -5 lambda, -6 Q, -7 ldq. */
 int skew_evd_tridiag_eig(skew_evd_handle h, int n, const double *alpha, int nev,
                          double *lambda, double *Q, int ldq);
+
+/* Band-width autotuner (not in the paper; Section 4.1 notes how strongly the
+ * speed of a reduction can depend on its block size).  Orders are grouped in
+ * size classes of 128 (n in (128(c-1), 128c]).  On the first call for a class
+ * and precision, a seeded synthetic skew matrix of order 128c (entries
+ * (u - u')/2 with u, u' independent and uniform in [-1, 1)) is solved on h's
+ * stream once per candidate band width {16, 32, 64}: one warm-up and three
+ * timed calls each, host wall clock.  The fastest band is cached in h and
+ * returned in *band; *ms (may be NULL) receives its best time per solve in
+ * milliseconds.  Later calls for the class return the cached values without
+ * solving.  Tuning allocates and frees its own device buffers (an input and
+ * outputs of order 128c) and grows h's workspace.
+ *   n          1 <= n <= SKEW_EVD_TUNE_NMAX
+ *   precision  SKEW_EVD_PREC_FP64 or SKEW_EVD_PREC_FP32_REFINE
+ * Errors: -1 h, -2 n, -3 precision, -4 band; SKEW_EVD_ERR_NOMEM if the tuning
+ * buffers cannot be allocated; a solver status if every candidate failed. */
+#define SKEW_EVD_TUNE_NMAX 8192
+int skew_evd_autotune(skew_evd_handle h, int n, int precision, int *band,
+                      double *ms);
 
 /* Text for a status code (static storage; for SKEW_EVD_ERR_HIP the text of the
  * most recent HIP error seen by this thread). */

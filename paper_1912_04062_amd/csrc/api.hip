@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 #include <algorithm>
+#include <chrono>
+#include <map>
 #include <thread>
 #include <vector>
 
@@ -67,6 +69,8 @@ struct skew_evd_handle_s {
     // batched form: sub-handles, each with its own stream and workspace
     std::vector<skew_evd_handle> sub;
     std::vector<hipStream_t> sub_streams;
+    // band-width autotuner: (precision, size class) -> (band, best wall ms)
+    std::map<int, std::pair<int, double>> tune;
 };
 
 namespace {
@@ -617,11 +621,14 @@ int check_device()
     return SKEW_EVD_OK;
 }
 
+// band widths with a panel kernel instance (band.hip): 8, 16, 32, 64
+bool band_supported(int b) { return b == 8 || b == 16 || b == 32 || b == 64; }
+
 int validate_opts(const skew_evd_opts *o)
 {
     if (!o) return 0;
     if (o->precision != SKEW_EVD_PREC_FP64 && o->precision != SKEW_EVD_PREC_FP32_REFINE) return 1;
-    if (o->band != 0 && (o->band < 8 || o->band > 64 || (o->band % 8) != 0)) return 1;
+    if (o->band != 0 && !band_supported(o->band)) return 1;
     if (o->max_refine_sweeps < 0) return 1;
     return 0;
 }
@@ -846,6 +853,126 @@ int skew_evd_destroy(skew_evd_handle h)
     return SKEW_EVD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Band-width autotuner.  The band width b (also the panel width of the
+// full-to-band stage) trades the MFMA efficiency of the rank-2b updates, which
+// grows with b, against the bulge chase and the stage-2 back-transformation,
+// whose work grows with b (about 6 n^2 b and 2 n^3 flops in b-long reflector
+// groups).  Orders are grouped in classes of TUNE_CLASS; for a class the tuner
+// solves a synthetic skew matrix of the class's largest order once per
+// candidate band (one warm-up and TUNE_REPS timed calls, wall clock, since
+// small solves are bound by their host synchronisations as much as by the
+// device) and keeps the fastest.  Results are cached in the handle.
+namespace {
+constexpr int TUNE_CLASS = 128;
+constexpr int TUNE_REPS = 3;
+const int TUNE_CAND[] = {16, 32, 64};
+
+int tune_class(int n) { return (n + TUNE_CLASS - 1) / TUNE_CLASS; }
+
+// Synthetic tuning input A = (B - B^T)/2, B with independent entries uniform
+// in [-1, 1) from splitmix64 (Steele, Lea and Flood, OOPSLA 2014).
+void tune_matrix(int n, std::vector<double> &A)
+{
+    A.assign((size_t)n * n, 0.0);
+    unsigned long long x = 0x5eed5eedULL + (unsigned long long)n;
+    auto next = [&]() {
+        unsigned long long z = (x += 0x9e3779b97f4a7c15ULL);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    };
+    for (int j = 0; j < n; ++j)
+        for (int i = j + 1; i < n; ++i) {
+            const double v = 0.5 * (next() - next());
+            A[i + (size_t)j * n] = v;
+            A[j + (size_t)i * n] = -v;
+        }
+}
+
+int tune_band(skew_evd_handle h, int n, int precision, size_t wslimit, int *band, double *ms)
+{
+    const int key = precision * 65536 + tune_class(n);
+    auto it = h->tune.find(key);
+    if (it != h->tune.end()) {
+        *band = it->second.first;
+        if (ms) *ms = it->second.second;
+        return SKEW_EVD_OK;
+    }
+    const int nr = tune_class(n) * TUNE_CLASS;
+    const int nev = (nr + 1) / 2;
+    std::vector<double> hA;
+    tune_matrix(nr, hA);
+    double *dA = nullptr, *dl = nullptr, *dzr = nullptr, *dzi = nullptr;
+    const size_t zb = sizeof(double) * (size_t)nr * nev;
+    if (hipMalloc(&dA, sizeof(double) * (size_t)nr * nr) != hipSuccess || hipMalloc(&dl, sizeof(double) * nev) != hipSuccess ||
+        hipMalloc(&dzr, zb) != hipSuccess || hipMalloc(&dzi, zb) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(dA);
+        (void)hipFree(dl);
+        (void)hipFree(dzr);
+        (void)hipFree(dzi);
+        return SKEW_EVD_ERR_NOMEM;
+    }
+    int rc = SKEW_EVD_OK;
+    hipError_t e = hipMemcpyAsync(dA, hA.data(), sizeof(double) * hA.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        set_hip_error(e, "autotune input copy");
+        rc = SKEW_EVD_ERR_HIP;
+    }
+    int best_b = 0, last_err = SKEW_EVD_OK;
+    double best_ms = 0.0;
+    for (int c = 0; rc == SKEW_EVD_OK && c < (int)(sizeof(TUNE_CAND) / sizeof(int)); ++c) {
+        const int b = TUNE_CAND[c];
+        if (b > nr - 2) continue;
+        skew_evd_opts o;
+        skew_evd_default_opts(&o);
+        o.precision = precision;
+        o.band = b;
+        o.workspace_limit = wslimit;
+        double tmin = 0.0;
+        int crc = SKEW_EVD_OK;
+        for (int r = 0; r <= TUNE_REPS && (crc == SKEW_EVD_OK || crc == SKEW_EVD_WARN_REFINE); ++r) {
+            const auto t0 = std::chrono::steady_clock::now();
+            crc = solve(h, nr, dA, nr, nev, dl, dzr, nr, dzi, nr, &o, nullptr);
+            const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (r == 1 || (r > 1 && t < tmin)) tmin = t;
+        }
+        if (crc != SKEW_EVD_OK && crc != SKEW_EVD_WARN_REFINE) {
+            last_err = crc;
+            if (crc == SKEW_EVD_ERR_HIP) rc = crc;   // the device is in error: stop
+            continue;
+        }
+        if (best_b == 0 || tmin < best_ms) {
+            best_b = b;
+            best_ms = tmin;
+        }
+    }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(dA);
+    (void)hipFree(dl);
+    (void)hipFree(dzr);
+    (void)hipFree(dzi);
+    if (rc) return rc;
+    if (best_b == 0) return last_err ? last_err : SKEW_EVD_ERR_NOCONV;
+    h->tune[key] = {best_b, best_ms};
+    *band = best_b;
+    if (ms) *ms = best_ms;
+    return SKEW_EVD_OK;
+}
+}  // namespace
+
+int skew_evd_autotune(skew_evd_handle h, int n, int precision, int *band, double *ms)
+{
+    if (!h) return -1;
+    if (n < 1 || n > SKEW_EVD_TUNE_NMAX) return -2;
+    if (precision != SKEW_EVD_PREC_FP64 && precision != SKEW_EVD_PREC_FP32_REFINE) return -3;
+    if (!band) return -4;
+    return tune_band(h, n, precision, 0, band, ms);
+}
+
 int skew_evd_ex(skew_evd_handle h, int n, const double *A, int lda, int nev, double *lambda, double *Z_re, int ldzr,
                 double *Z_im, int ldzi, const skew_evd_opts *opts, skew_evd_info *info)
 {
@@ -862,6 +989,15 @@ int skew_evd_ex(skew_evd_handle h, int n, const double *A, int lda, int nev, dou
     if (validate_opts(opts)) return -11;
     if (info) memset(info, 0, sizeof(*info));
     if (n == 0 || nev == 0) return SKEW_EVD_OK;
+    skew_evd_opts tuned;
+    if (opts && opts->autotune && opts->band == 0 && n <= SKEW_EVD_TUNE_NMAX) {
+        int b = 0;
+        int rc = tune_band(h, n, opts->precision, opts->workspace_limit, &b, nullptr);
+        if (rc) return rc;
+        tuned = *opts;
+        tuned.band = b;
+        opts = &tuned;
+    }
     return solve(h, n, A, lda, nev, lambda, Z_re, ldzr, Z_im, ldzi, opts, info);
 }
 
@@ -938,6 +1074,20 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
         h->sub.push_back(sh);
         h->sub_streams.push_back(s2);
     }
+    // autotuned band widths: each size class is tuned once on h, before the
+    // problems are dealt out; the sub-handles then solve with a fixed band
+    std::vector<skew_evd_opts> popt(count);
+    for (int i = 0; i < count; ++i) {
+        if (opts) popt[i] = *opts;
+        else skew_evd_default_opts(&popt[i]);
+        if (popt[i].autotune && popt[i].band == 0 && n[i] >= 1 && n[i] <= SKEW_EVD_TUNE_NMAX) {
+            int b = 0;
+            int rc = tune_band(h, n[i], popt[i].precision, popt[i].workspace_limit, &b, nullptr);
+            if (rc) return rc;
+            popt[i].band = b;
+        }
+        popt[i].autotune = 0;
+    }
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
@@ -961,7 +1111,7 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
             for (int i : part[s2]) {
                 skew_evd_info one;
                 status[i] = skew_evd_ex(h->sub[s2], n[i], A[i], lda[i], nev[i], lambda[i], Z_re[i], std::max(1, n[i]),
-                                        Z_im[i], std::max(1, n[i]), opts, &one);
+                                        Z_im[i], std::max(1, n[i]), &popt[i], &one);
                 sinfo[s2].ms_total += one.ms_total;
                 for (int k = 0; k < 8; ++k) sinfo[s2].ms_stage[k] += one.ms_stage[k];
                 sinfo[s2].band = one.band;
@@ -992,7 +1142,7 @@ int skew_evd_band_reduce(skew_evd_handle h, int n, const double *A, int lda, int
     if (n < 0) return -2;
     if (n > 0 && !A) return -3;
     if (lda < std::max(1, n)) return -4;
-    if (b < 8 || b > 64 || b % 8) return -5;
+    if (!band_supported(b)) return -5;
     if (n > 0 && !band) return -6;
     if (ldband < b + 1) return -7;
     if (n == 0) return SKEW_EVD_OK;
@@ -1016,7 +1166,7 @@ int skew_evd_tridiagonalize(skew_evd_handle h, int n, const double *A, int lda, 
     if (n < 0) return -2;
     if (n > 0 && !A) return -3;
     if (lda < std::max(1, n)) return -4;
-    if (b != 0 && (b < 8 || b > 64 || b % 8)) return -5;
+    if (b != 0 && !band_supported(b)) return -5;
     if (n > 1 && !alpha) return -6;
     if (n <= 1) return SKEW_EVD_OK;
     Plan p = make_plan(n, 0, b, 0);

@@ -30,7 +30,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("band", ctypes.c_int),
                 ("max_refine_sweeps", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("workspace_limit", ctypes.c_size_t), ("profile", ctypes.c_int),
-                ("reserved", ctypes.c_int * 7)]
+                ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
 
 
 class KStat(ctypes.Structure):
@@ -101,6 +101,8 @@ def _load():
     lib.skew_evd_tridiag_eig.restype = ip
     lib.skew_evd_status_string.argtypes = [ip]
     lib.skew_evd_status_string.restype = ctypes.c_char_p
+    lib.skew_evd_autotune.argtypes = [vp, ip, ip, ctypes.POINTER(ip), ctypes.POINTER(ctypes.c_double)]
+    lib.skew_evd_autotune.restype = ip
     lib.skew_evd_version.argtypes = []
     lib.skew_evd_version.restype = ip
     _lib = lib
@@ -116,7 +118,7 @@ def status_string(status):
 
 
 def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=None,
-                 workspace_limit=0, profile=0):
+                 workspace_limit=0, profile=0, autotune=0):
     o = Opts()
     _load().skew_evd_default_opts(ctypes.byref(o))
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
@@ -127,6 +129,7 @@ def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=No
         o.refine_tol = float(refine_tol)
     o.workspace_limit = int(workspace_limit)
     o.profile = int(profile)
+    o.autotune = int(autotune)
     return o
 
 
@@ -200,7 +203,18 @@ class Handle:
         self.last_info = inf
         return lam[:nev], zr[:n, :nev], zi[:n, :nev]
 
-    def solve_batched(self, mats, precision="fp64", band=0):
+    def autotune(self, n, precision="fp64"):
+        """Band width the autotuner picks for order n (tuned once per size
+        class and cached in the handle); returns (band, best ms per solve)."""
+        b = ctypes.c_int(0)
+        ms = ctypes.c_double(0.0)
+        prec = _PREC[precision] if isinstance(precision, str) else int(precision)
+        st = self._lib.skew_evd_autotune(self._h, int(n), prec, ctypes.byref(b), ctypes.byref(ms))
+        if st != OK:
+            raise SkewEvdError(st, "skew_evd_autotune")
+        return b.value, ms.value
+
+    def solve_batched(self, mats, precision="fp64", band=0, autotune=0):
         """Solve a list of skew matrices (each n_i x n_i float64 CUDA); returns
         a list of (lam, Zre, Zim) and the per-problem status list."""
         count = len(mats)
@@ -221,7 +235,7 @@ class Handle:
         zr_a = PtrA(*[o[1].data_ptr() for o in outs])
         zi_a = PtrA(*[o[2].data_ptr() for o in outs])
         status = IntA()
-        o = default_opts(precision, band)
+        o = default_opts(precision, band, autotune=autotune)
         inf = Info()
         st = self._lib.skew_evd_batched(self._h, count, n_a, A_a, lda_a, nev_a, l_a, zr_a, zi_a,
                                         ctypes.byref(o), ctypes.byref(inf), status)

@@ -31,7 +31,7 @@ def test_header_declares_entry_points():
     for must in ["skew_evd", "skew_evd_ex", "skew_evd_batched", "skew_evd_create",
                  "skew_evd_destroy", "skew_evd_status_string", "skew_evd_band_reduce",
                  "skew_evd_tridiagonalize", "skew_evd_tridiag_eig", "skew_evd_default_opts",
-                 "skew_evd_version"]:
+                 "skew_evd_version", "skew_evd_autotune"]:
         assert must in names
 
 
@@ -53,6 +53,8 @@ def test_argument_validation_without_device(lib):
     assert lib.skew_evd(0, None, 1, 0, None, None, None) == 0
     lib.skew_evd_ex.restype = ctypes.c_int
     assert lib.skew_evd_ex(None, 4, vp(8), 4, 1, vp(8), vp(8), 4, vp(8), 4, None, None) == -1
+    lib.skew_evd_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
+    assert lib.skew_evd_autotune(None, 100, 0, vp(8), None) == -1
 
 
 def test_status_strings(lib):
