@@ -41,7 +41,10 @@ extern "C" {
 #define SKEW_EVD_OK 0
 #define SKEW_EVD_ERR_NONFINITE 1   /* NaN or Inf in the strict lower triangle */
 #define SKEW_EVD_ERR_NOCONV 2      /* tridiagonal solver or a device wait did not finish */
-#define SKEW_EVD_WARN_REFINE 3     /* refinement stopped above its tolerance (results valid, best iterate) */
+#define SKEW_EVD_WARN_REFINE 3     /* reserved: a precision-form solve whose refinement stops above
+                                      its tolerance (or meets pairs closer than its start resolves)
+                                      is solved again in the FP64 form (info->refine_sweeps = -1),
+                                      so the solvers do not return this code */
 #define SKEW_EVD_ERR_NOMEM 4       /* workspace allocation failed or exceeds opts.workspace_limit */
 #define SKEW_EVD_ERR_HIP 5         /* HIP runtime error; text from skew_evd_status_string */
 #define SKEW_EVD_ERR_NODEVICE 6    /* no usable gfx950 device */
@@ -55,7 +58,7 @@ typedef struct skew_evd_opts {
     int band;               /* semi-bandwidth b of the intermediate band matrix
                                (= panel width of the full-to-band stage); 0 = auto.
                                Supported: 8, 16, 32, 64 */
-    int max_refine_sweeps;  /* precision form: refinement sweeps (default 2) */
+    int max_refine_sweeps;  /* precision form: refinement sweeps (default 3) */
     double refine_tol;      /* precision form: stop when the normalised
                                residual estimate is below this (default 1e-14) */
     size_t workspace_limit; /* bytes; 0 = unlimited.  Exceeding it returns NOMEM */

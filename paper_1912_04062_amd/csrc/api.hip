@@ -675,12 +675,16 @@ int refine(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, i
         if (o.max_refine_sweeps == 0) break;
         const double omega = 64.0 * 2.220446049250313e-16 * lmax;
         unsigned *nclust = (unsigned *)(stat + 4);
+        double *emax = stat + 5;
         skew::launch_refine_update(ptr<double>(h, L.rS), ptr<double>(h, L.rG), n, ncx, nblk, odd,
-                                   ptr<double>(h, L.rlam), omega, ptr<float>(h, L.rE), X, Xn, nclust, st);
+                                   ptr<double>(h, L.rlam), omega, ptr<float>(h, L.rE), X, Xn, nclust, emax, st);
         HCHK(hipGetLastError());
-        unsigned hc = 0;
-        HCHK(hipMemcpyAsync(&hc, nclust, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        double hb[2] = {0.0, 0.0};
+        HCHK(hipMemcpyAsync(hb, stat + 4, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
         HCHK(hipStreamSynchronize(st));
+        unsigned hc = 0;
+        memcpy(&hc, &hb[0], sizeof(unsigned));
+        const double ecor = hb[1];
         if (hc) {
             // near-degenerate pairs the FP32 start cannot separate: not refinable here
             *sweeps_out = sweeps;
@@ -689,8 +693,10 @@ int refine(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, i
         }
         std::swap(X, Xn);
         ++sweeps;
-        // a Newton step from a residual r leaves about r^2 (quadratic convergence)
-        if (last * last <= o.refine_tol) {
+        // a Newton step from an error r whose largest pair correction is e
+        // leaves about r * e (r^2 / gap): the quadratic rate holds only for
+        // well-separated pairs, so the shortcut takes the correction into account
+        if (last * std::max(ecor, last) <= o.refine_tol) {
             converged = true;
             break;
         }
@@ -745,8 +751,9 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     if (prec) {
         HCHK(kt_begin(h, SKEW_EVD_K_REFINE));
         refine_rc = refine(h, p, L, A, lda, o, nev_out, lambda, Z_re, ldzr, Z_im, ldzi, &rsweeps, &rres);
-        if (refine_rc == SKEW_EVD_REFINE_CLUSTER) {
-            // clusters closer than the FP32 pipeline resolves: fall back to the FP64 form
+        if (refine_rc == SKEW_EVD_REFINE_CLUSTER || refine_rc == SKEW_EVD_WARN_REFINE) {
+            // clusters closer than the FP32 pipeline resolves, or no convergence
+            // within max_refine_sweeps: fall back to the FP64 form
             skew_evd_opts o64 = o;
             o64.precision = SKEW_EVD_PREC_FP64;
             int rc64 = solve(h, n, A, lda, nev_out, lambda, Z_re, ldzr, Z_im, ldzi, &o64, info);
@@ -811,7 +818,7 @@ void skew_evd_default_opts(skew_evd_opts *opts)
     memset(opts, 0, sizeof(*opts));
     opts->precision = SKEW_EVD_PREC_FP64;
     opts->band = 0;
-    opts->max_refine_sweeps = 2;
+    opts->max_refine_sweeps = 3;
     opts->refine_tol = 1e-14;
     opts->workspace_limit = 0;
 }

@@ -92,6 +92,7 @@ void launch_refine_products(const double *A, int lda, int n, const double *X, in
 void launch_refine_eigs(const double *S, const double *G, int ncx, int nblk, int odd, double *lam, double *stat,
                         hipStream_t st);
 void launch_refine_update(const double *S, const double *G, int n, int ncx, int nblk, int odd, const double *lam,
-                          double omega, float *E, const double *X, double *Xn, unsigned *nclust, hipStream_t st);
+                          double omega, float *E, const double *X, double *Xn, unsigned *nclust, double *emax,
+                          hipStream_t st);
 
 }  // namespace skew

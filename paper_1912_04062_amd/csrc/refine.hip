@@ -182,76 +182,88 @@ __global__ __launch_bounds__(256) void k_stats(const double *__restrict__ S, con
 // E (ncx x ncx, type TE): one thread per block pair (p, q).
 template <typename TE>
 __global__ void k_eform(const double *__restrict__ S, const double *__restrict__ G, int ncx, int nblk, int odd,
-                        const double *__restrict__ lam, double omega, TE *__restrict__ E, unsigned *nclust)
+                        const double *__restrict__ lam, double omega, TE *__restrict__ E, unsigned *nclust,
+                        double *emax)
 {
     const int p = blockIdx.x * 16 + threadIdx.x % 16;
     const int q = blockIdx.y * 16 + threadIdx.x / 16;
-    if (p >= nblk || q >= nblk) return;
-    const int cp = blk_col(p, odd), sp = blk_size(p, odd);
-    const int cq = blk_col(q, odd), sq = blk_size(q, odd);
-    // S(i, j) and R(i, j) for any i, j from the lower triangles
-    auto Sv = [&](int i, int j) -> double {
-        if (i == j) return 0.0;
-        return i > j ? S[(size_t)j * ncx + i] : -S[(size_t)i * ncx + j];
-    };
-    auto Rv = [&](int i, int j) -> double {
-        double g = i >= j ? G[(size_t)j * ncx + i] : G[(size_t)i * ncx + j];
-        return (i == j ? 1.0 : 0.0) - g;
-    };
-    double e[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    if (p == q) {
-        for (int a = 0; a < sp; ++a)
-            for (int b = 0; b < sq; ++b) e[a][b] = 0.5 * Rv(cp + a, cq + b);
-    } else {
-        const double a = lam[p], c = lam[q];
-        double C[2][2];
-        // C = -S_pq - R_pq D_q,  D_q = c J (J = [[0,1],[-1,0]]):  (R J)[i][0] = -R[i][1], (R J)[i][1] = R[i][0]
-        for (int i = 0; i < sp; ++i)
-            for (int j = 0; j < sq; ++j) {
-                double rj = 0.0;
-                if (sq == 2) rj = (j == 0) ? -Rv(cp + i, cq + 1) : Rv(cp + i, cq + 0);
-                C[i][j] = -Sv(cp + i, cq + j) - c * rj;
+    double macc = 0.0;      // largest accepted off-diagonal correction of this thread
+    if (p < nblk && q < nblk) {
+        const int cp = blk_col(p, odd), sp = blk_size(p, odd);
+        const int cq = blk_col(q, odd), sq = blk_size(q, odd);
+        // S(i, j) and R(i, j) for any i, j from the lower triangles
+        auto Sv = [&](int i, int j) -> double {
+            if (i == j) return 0.0;
+            return i > j ? S[(size_t)j * ncx + i] : -S[(size_t)i * ncx + j];
+        };
+        auto Rv = [&](int i, int j) -> double {
+            double g = i >= j ? G[(size_t)j * ncx + i] : G[(size_t)i * ncx + j];
+            return (i == j ? 1.0 : 0.0) - g;
+        };
+        double e[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        if (p == q) {
+            for (int a = 0; a < sp; ++a)
+                for (int b = 0; b < sq; ++b) e[a][b] = 0.5 * Rv(cp + a, cq + b);
+        } else {
+            const double a = lam[p], c = lam[q];
+            double C[2][2];
+            // C = -S_pq - R_pq D_q,  D_q = c J (J = [[0,1],[-1,0]]):  (R J)[i][0] = -R[i][1], (R J)[i][1] = R[i][0]
+            for (int i = 0; i < sp; ++i)
+                for (int j = 0; j < sq; ++j) {
+                    double rj = 0.0;
+                    if (sq == 2) rj = (j == 0) ? -Rv(cp + i, cq + 1) : Rv(cp + i, cq + 0);
+                    C[i][j] = -Sv(cp + i, cq + j) - c * rj;
+                }
+            if (fabs(a - c) <= omega) {
+                for (int i = 0; i < sp; ++i)
+                    for (int j = 0; j < sq; ++j) e[i][j] = 0.5 * Rv(cp + i, cq + j);
+            } else if (sp == 2 && sq == 2) {
+                // M = J C
+                const double M00 = C[1][0], M01 = C[1][1], M10 = -C[0][0], M11 = -C[0][1];
+                // J M J = [[-M11, M10], [M01, -M00]]
+                const double c00 = 0.5 * (M00 + M11), c01 = 0.5 * (M01 - M10);
+                const double a00 = 0.5 * (M00 - M11), a01 = 0.5 * (M01 + M10);
+                // commuting part [[c00, c01], [-c01, c00]], anti part [[a00, a01], [a01, -a00]]
+                const double ic = -1.0 / (a - c), ia = -1.0 / (a + c);
+                e[0][0] = ic * c00 + ia * a00;
+                e[0][1] = ic * c01 + ia * a01;
+                e[1][0] = -ic * c01 + ia * a01;
+                e[1][1] = ic * c00 - ia * a00;
+            } else if (sp == 1 && sq == 2) {
+                // -c E J = C  ->  E = C J / c :  (C J)[0][0] = -C[0][1], (C J)[0][1] = C[0][0]
+                e[0][0] = -C[0][1] / c;
+                e[0][1] = C[0][0] / c;
+            } else if (sp == 2 && sq == 1) {
+                // a J E = C  ->  E = -J C / a :  (J C)[0][0] = C[1][0], (J C)[1][0] = -C[0][0]
+                e[0][0] = -C[1][0] / a;
+                e[1][0] = C[0][0] / a;
             }
-        if (fabs(a - c) <= omega) {
-            for (int i = 0; i < sp; ++i)
-                for (int j = 0; j < sq; ++j) e[i][j] = 0.5 * Rv(cp + i, cq + j);
-        } else if (sp == 2 && sq == 2) {
-            // M = J C
-            const double M00 = C[1][0], M01 = C[1][1], M10 = -C[0][0], M11 = -C[0][1];
-            // J M J = [[-M11, M10], [M01, -M00]]
-            const double c00 = 0.5 * (M00 + M11), c01 = 0.5 * (M01 - M10);
-            const double a00 = 0.5 * (M00 - M11), a01 = 0.5 * (M01 + M10);
-            // commuting part [[c00, c01], [-c01, c00]], anti part [[a00, a01], [a01, -a00]]
-            const double ic = -1.0 / (a - c), ia = -1.0 / (a + c);
-            e[0][0] = ic * c00 + ia * a00;
-            e[0][1] = ic * c01 + ia * a01;
-            e[1][0] = -ic * c01 + ia * a01;
-            e[1][1] = ic * c00 - ia * a00;
-        } else if (sp == 1 && sq == 2) {
-            // -c E J = C  ->  E = C J / c :  (C J)[0][0] = -C[0][1], (C J)[0][1] = C[0][0]
-            e[0][0] = -C[0][1] / c;
-            e[0][1] = C[0][0] / c;
-        } else if (sp == 2 && sq == 1) {
-            // a J E = C  ->  E = -J C / a :  (J C)[0][0] = C[1][0], (J C)[1][0] = -C[0][0]
-            e[0][0] = -C[1][0] / a;
-            e[1][0] = C[0][0] / a;
         }
-    }
-    // a Newton step is only valid for small corrections: a pair whose solution
-    // is not small is near-degenerate at this accuracy; it keeps E = R/2 and is
-    // counted (the caller then solves the problem in FP64 instead)
-    if (p != q) {
-        double mx = 0.0;
+        // a Newton step is only valid for small corrections: a pair whose solution
+        // is not small is near-degenerate at this accuracy; it keeps E = R/2 and is
+        // counted (the caller then solves the problem in FP64 instead)
+        if (p != q) {
+            double mx = 0.0;
+            for (int i = 0; i < sp; ++i)
+                for (int j = 0; j < sq; ++j) mx = fmax(mx, fabs(e[i][j]));
+            if (!(mx <= 0.25)) {
+                for (int i = 0; i < sp; ++i)
+                    for (int j = 0; j < sq; ++j) e[i][j] = 0.5 * Rv(cp + i, cq + j);
+                atomicAdd(nclust, 1u);
+            } else {
+                macc = mx;
+            }
+        }
         for (int i = 0; i < sp; ++i)
-            for (int j = 0; j < sq; ++j) mx = fmax(mx, fabs(e[i][j]));
-        if (!(mx <= 0.25)) {
-            for (int i = 0; i < sp; ++i)
-                for (int j = 0; j < sq; ++j) e[i][j] = 0.5 * Rv(cp + i, cq + j);
-            atomicAdd(nclust, 1u);
-        }
+            for (int j = 0; j < sq; ++j) E[(size_t)(cq + j) * ncx + cp + i] = (TE)e[i][j];
     }
-    for (int i = 0; i < sp; ++i)
-        for (int j = 0; j < sq; ++j) E[(size_t)(cq + j) * ncx + cp + i] = (TE)e[i][j];
+    // the largest correction bounds what the step leaves behind (about the
+    // current error times it); one atomic per workgroup
+    __shared__ double red[4];
+    macc = wave_max(macc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = macc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomic_max_pos(emax, fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
 }
 
 // Xn = X + X E  (ncx x ncx E), the product on the MFMA of type T.
@@ -319,10 +331,11 @@ void launch_refine_eigs(const double *S, const double *G, int ncx, int nblk, int
 }
 
 void launch_refine_update(const double *S, const double *G, int n, int ncx, int nblk, int odd, const double *lam,
-                          double omega, float *E, const double *X, double *Xn, unsigned *nclust, hipStream_t st)
+                          double omega, float *E, const double *X, double *Xn, unsigned *nclust, double *emax,
+                          hipStream_t st)
 {
     hipLaunchKernelGGL(k_eform<float>, dim3(cdiv(nblk, 16), cdiv(nblk, 16)), dim3(256), 0, st, S, G, ncx, nblk, odd,
-                       lam, omega, E, nclust);
+                       lam, omega, E, nclust, emax);
     dim3 g(cdiv(n, 128), cdiv(ncx, 128));
     hipLaunchKernelGGL((k_xe<float, float, 128, 128>), g, dim3(256), (gemm::smem_bytes<float, 128, 128>()), st, X,
                        (const float *)E, n, ncx, Xn);

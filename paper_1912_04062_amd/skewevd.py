@@ -5,8 +5,10 @@ kernels behind the C-ABI of include/skew_evd.h.  PyTorch supplies device
 memory and the current stream.  The library must have been built (see
 paper_1912_04062_amd/build.py); importing this module without it raises.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -148,6 +150,22 @@ def empty_colmajor(n, k, device, dtype=torch.float64):
     return torch.empty((k, n), dtype=dtype, device=device).t()
 
 
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # Handles still alive at exit (for instance held by the traceback of an
+    # uncaught exception) are destroyed here, while torch and the HIP runtime
+    # are intact, instead of during interpreter finalization.  This module is
+    # imported after torch, so this runs before torch's own exit handlers.
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
 class Handle:
     """A solver handle bound to the current device and a torch stream."""
 
@@ -160,6 +178,7 @@ class Handle:
         if st != 0:
             raise SkewEvdError(st, "skew_evd_create")
         self._h = h
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -167,6 +186,9 @@ class Handle:
             self._h = None
 
     def __del__(self):
+        import sys
+        if sys.is_finalizing():
+            return          # the runtime may be gone; _close_all ran before this
         try:
             self.close()
         except Exception:

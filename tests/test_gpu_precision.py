@@ -51,3 +51,34 @@ def test_fp32_odd_null(h):
     assert lam[0] == 0.0
     assert np.all(Z[:, 0].imag == 0.0)
     assert np.linalg.norm(A @ Z[:, 0].real) <= 1e-13 * lam.max() * np.sqrt(n)
+
+
+def test_fp32_refine_uneven_batch_matrices(h):
+    """Every matrix of the uneven batch (512 orders in 64..1024, seed 5) solved
+    one by one in the precision form.  Some of them hold pairs closer than the
+    FP32 start resolves; their refinement must either converge or hand the
+    problem to the FP64 form: every result meets the FP64 tolerances."""
+    import torch
+    sizes, mats = wl.batch(512, 5)
+    print(f"fp32+refine on {len(sizes)} batch matrices, n in [{min(sizes)}, {max(sizes)}]", flush=True)
+    worst_r, worst_o, fallbacks = 0.0, 0.0, 0
+    for i, A in enumerate(mats):
+        n = A.shape[0]
+        Ad = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+        lam, zr, zi = h.solve(Ad, precision="fp32")
+        fallbacks += h.last_info.refine_sweeps < 0
+        Af = torch.tril(Ad.contiguous(), -1)
+        Af = Af - Af.t()
+        Z = torch.complex(zr.contiguous(), zi.contiguous())
+        R = torch.complex(Af, torch.zeros_like(Af)) @ Z - Z * (1j * lam)[None, :]
+        nA = lam.max().item()
+        r = torch.linalg.norm(R).item() / (n * nA)
+        G = Z.conj().t() @ Z
+        G.diagonal().sub_(1.0)
+        o = torch.linalg.norm(G).item() / n
+        assert r <= TOL_RES and o <= TOL_ORTH, (i, n, r, o, h.last_info.refine_sweeps)
+        worst_r, worst_o = max(worst_r, r), max(worst_o, o)
+        if i % 64 == 0:                              # oracle sample
+            lref, _ = oracle.skew_evd(A)
+            assert np.max(np.abs(lam.cpu().numpy() - lref)) <= TOL_EIG * lref.max()
+    print(f"  worst res={worst_r:.2e} orth={worst_o:.2e}, FP64 fallbacks {fallbacks}", flush=True)
