@@ -178,10 +178,12 @@ Layout plan_layout(const Plan &p)
 // control words
 enum { CTL_FLAGS = 0, CTL_ERR = 1, CTL_BAR = 2, CTL_QRFLAG = 3, CTL_HHHAND = 4, CTL_PROGRESS = 64 };
 
+// Fixed band rule (opts.band = 0 without the autotuner).  The autotuner
+// picks 64 for every size class from 128 to 1024 on gfx950: the wider panels'
+// MFMA efficiency outweighs the longer bulge chase there too.
 int auto_band(int n)
 {
-    if (n >= 2048) return 64;
-    if (n >= 128) return 32;
+    if (n >= 128) return 64;
     return 16;
 }
 
