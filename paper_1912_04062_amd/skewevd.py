@@ -8,6 +8,7 @@ paper_1912_04062_amd/build.py); importing this module without it raises.
 import atexit
 import ctypes
 import os
+import sys
 import weakref
 
 import torch
@@ -186,7 +187,6 @@ class Handle:
             self._h = None
 
     def __del__(self):
-        import sys
         if sys.is_finalizing():
             return          # the runtime may be gone; _close_all ran before this
         try:
