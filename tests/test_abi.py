@@ -73,3 +73,35 @@ def test_oracle_shares_nothing_with_the_library():
     for f in os.listdir(os.path.join(ROOT, "paper_1912_04062_amd", "csrc")):
         txt = open(os.path.join(ROOT, "paper_1912_04062_amd", "csrc", f)).read()
         assert "oracle" not in txt.lower()
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of skew_evd_opts / skew_evd_info have the
+    C layout: sizes and field offsets from a program compiled against the header."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    from paper_1912_04062_amd import skewevd as s
+    fields = {"skew_evd_opts": (s.Opts, ["precision", "band", "max_refine_sweeps", "refine_tol",
+                                         "workspace_limit", "profile", "autotune", "reserved"]),
+              "skew_evd_info": (s.Info, ["ms_total", "ms_stage", "band", "refine_sweeps",
+                                         "refine_residual", "workspace_bytes", "kern"])}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "skew_evd.h"', "int main(void) {"]
+    for cname, (_, names) in fields.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f in names:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = []
+    for _, (cls, names) in fields.items():
+        want.append(ctypes.sizeof(cls))
+        want += [getattr(cls, f).offset for f in names]
+    assert got == want
