@@ -148,7 +148,10 @@ int skew_evd(int n, const double *A, int lda, int nev,
  * and device pointers), each solved as by skew_evd_ex with ldz = n[i].
  * status[i] (host) receives each problem's status; the return value is the
  * first non-zero status (or a negative argument error: -2 count, -3 n,
- * -4 A, -5 lda, -6 nev, -7 lambda, -8 Z_re, -9 Z_im, -12 status). */
+ * -4 A, -5 lda, -6 nev, -7 lambda, -8 Z_re, -9 Z_im, -12 status).  With
+ * opts->autotune, each size class is tuned on h before any problem is solved;
+ * if tuning fails, no problem is solved and every status[i] holds the
+ * tuner's status, which is also returned. */
 int skew_evd_batched(skew_evd_handle h, int count, const int *n,
                      const double *const *A, const int *lda, const int *nev,
                      double *const *lambda, double *const *Z_re,

@@ -1092,7 +1092,11 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
         if (popt[i].autotune && popt[i].band == 0 && n[i] >= 1 && n[i] <= SKEW_EVD_TUNE_NMAX) {
             int b = 0;
             int rc = tune_band(h, n[i], popt[i].precision, popt[i].workspace_limit, &b, nullptr);
-            if (rc) return rc;
+            if (rc) {
+                // nothing was solved: every problem reports the tuner's status
+                for (int k = 0; k < count; ++k) status[k] = rc;
+                return rc;
+            }
             popt[i].band = b;
         }
         popt[i].autotune = 0;
