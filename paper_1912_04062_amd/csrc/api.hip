@@ -60,15 +60,24 @@ struct skew_evd_handle_s {
     std::vector<KRec> krec;
     size_t kopen[SKEW_EVD_NKERN] = {};
     int refine_passes = 0;
-    int *goff_host = nullptr;       // pinned group offsets of the bulge-chase reflectors
-    size_t goff_cap = 0;
+    bool async = false;             // enqueue only: no stage events, no host waits (batched form)
+    double *lam_host = nullptr;     // pinned: eigenvalues, ||T||, then the polishing shifts
+    size_t lam_cap = 0;
+    int polish_lo = 0, polish_hi = 0;   // vectors [lo, hi) get the polishing step
+    std::vector<int> win0;          // per Gram-Schmidt block: first vector of its window
+    hipEvent_t win_ev = nullptr;    // the eigenvalues' copy to lam_host is complete
+    unsigned debug = 0;             // opts.debug of the current call
     // second stream: the T factors of the stage-2 groups run on it beside
     // the tridiagonal solve
     hipStream_t aux = nullptr;
     hipEvent_t aux_ev[3] = {};
-    // batched form: sub-handles, each with its own stream and workspace
-    std::vector<skew_evd_handle> sub;
+    // batched form: sub-streams with an event each, a fork event, and pinned
+    // host images of the batched chase's descriptors and the status words
     std::vector<hipStream_t> sub_streams;
+    std::vector<hipEvent_t> bev;
+    hipEvent_t bev0 = nullptr;
+    char *bhost = nullptr;
+    size_t bhost_cap = 0;
     // band-width autotuner: (precision, size class) -> (band, best wall ms)
     std::map<int, std::pair<int, double>> tune;
 };
@@ -79,7 +88,7 @@ namespace {
 // Workspace layout.  Offsets are 256-byte aligned.
 struct Layout {
     size_t W, Vall, Tall, tauall, Ypart, Y0, Wd, Gp, Tx, part, ab, goff, V2, tau2, T2, V2t, alpha, a2, stats,
-        lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, Qd, Z, cq, cqGp, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
+        lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, pshift, Qd, Z, cq, cqGp, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
         rstat, Tm, total;
     std::vector<size_t> Voff;
 };
@@ -144,13 +153,16 @@ Layout plan_layout(const Plan &p)
     L.Sw = take(n * nev);
     L.Yiv = take(sizeof(double) * n * nev);
     L.ivfac = take(sizeof(double) * 2 * nev);
+    L.pshift = take(sizeof(double) * nev);
     L.Qd = take(sizeof(double) * n * nev);
     L.Z = take(es * n * 2 * nev);
     L.cq = take(sizeof(double) * skew::cholqr_scratch_doubles());
     L.cqGp = take(sizeof(double) * (size_t)cholqr_max_splits() * b * b);
     L.Wp = take(sizeof(double) * tn_parts_max() * b * 2 * nev);
     L.Wt2 = take(sizeof(double) * 2 * b * 2 * nev);
-    const size_t wmax = std::max((size_t)p.orth_window, (size_t)ORTH_NB);
+    // a window covers at least orth_window earlier vectors and grows to every
+    // earlier vector of a cluster (up to nev)
+    const size_t wmax = std::max((size_t)p.nev, (size_t)ORTH_NB);
     L.Pp = take(sizeof(double) * tn_parts_max() * wmax * ORTH_NB);
     L.P = take(sizeof(double) * wmax * ORTH_NB);
     L.Gp2 = take(sizeof(double) * tn_parts_max() * ORTH_NB * ORTH_NB);
@@ -212,6 +224,7 @@ int ensure_ws(skew_evd_handle h, size_t bytes, size_t limit)
     if (bytes <= h->ws_bytes) return SKEW_EVD_OK;
     if (h->ws) {
         HCHK(hipStreamSynchronize(h->stream));
+        if (h->aux) HCHK(hipStreamSynchronize(h->aux));
         HCHK(hipFree(h->ws));
         h->ws = nullptr;
         h->ws_bytes = 0;
@@ -228,6 +241,13 @@ int ensure_ws(skew_evd_handle h, size_t bytes, size_t limit)
 }
 
 template <typename T> T *ptr(skew_evd_handle h, size_t off) { return (T *)(h->ws + off); }
+
+// stage event i on the handle's stream (none in the enqueue-only mode)
+hipError_t ev_record(skew_evd_handle h, int i)
+{
+    if (h->async || !h->ev[i]) return hipSuccess;
+    return hipEventRecord(h->ev[i], h->stream);
+}
 
 // Kernel timers: an event before and after the launches of a main kernel.
 hipError_t kt_event(skew_evd_handle h, size_t *idx)
@@ -323,7 +343,7 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
     skew::launch_ingest<T>(A, lda, n, W, n, ctl + CTL_FLAGS, st);
     HCHK(hipGetLastError());
     (void)check_finite;   // the non-finite flag is read when the call completes
-    HCHK(hipEventRecord(h->ev[1], st));
+    HCHK(ev_record(h, 1));
     unsigned bar_base = 0;
     for (int j = 0; j < p.npanels; ++j) {
         const int c0 = j * b, r0 = c0 + b, m = n - r0;
@@ -372,50 +392,141 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
     }
     skew::launch_band_extract<T>(W, n, n, b, ptr<double>(h, L.ab), 2 * b + 1, st);
     HCHK(hipGetLastError());
-    HCHK(hipEventRecord(h->ev[2], st));
+    HCHK(ev_record(h, 2));
     return SKEW_EVD_OK;
+}
+
+// Everything the chase needs besides the band: the group offsets of its
+// reflectors (device-side), zeroed reflector storage, counters and ticket.
+void chase_prepare(skew_evd_handle h, const Plan &p, const Layout &L)
+{
+    hipStream_t st = h->stream;
+    const int n = p.n, b = p.b;
+    skew::launch_goff(n, b, p.nb2, ptr<int>(h, L.goff), st);
+    if (p.ngroups > 0) {
+        skew::launch_fill32(ptr<double>(h, L.V2), 0u, 2 * (size_t)p.ngroups * b * p.nb2, st);
+        skew::launch_fill32(ptr<double>(h, L.tau2), 0u, 2 * (size_t)p.ngroups * p.nb2, st);
+    }
+    skew::launch_fill32(ptr<unsigned>(h, L.ctl) + CTL_PROGRESS, 0u, (size_t)n, st);   // counters and the ticket
 }
 
 int stage_chase(skew_evd_handle h, const Plan &p, const Layout &L)
 {
     hipStream_t st = h->stream;
     const int n = p.n, b = p.b;
-    if ((size_t)(p.nsig + 2) > h->goff_cap) {
-        if (h->goff_host) HCHK(hipHostFree(h->goff_host));
-        h->goff_host = nullptr;
-        h->goff_cap = 0;
-        HCHK(hipHostMalloc((void **)&h->goff_host, sizeof(int) * (p.nsig + 2), hipHostMallocDefault));
-        h->goff_cap = p.nsig + 2;
-    }
-    int *goff = h->goff_host;
-    skew::chase_ngroups(n, b, p.nb2, goff);
-    HCHK(hipMemcpyAsync(ptr<int>(h, L.goff), goff, sizeof(int) * (p.nsig + 1), hipMemcpyHostToDevice, st));
-    if (p.ngroups > 0) {
-        HCHK(hipMemsetAsync(ptr<double>(h, L.V2), 0, sizeof(double) * (size_t)p.ngroups * b * p.nb2, st));
-        HCHK(hipMemsetAsync(ptr<double>(h, L.tau2), 0, sizeof(double) * (size_t)p.ngroups * p.nb2, st));
-    }
+    chase_prepare(h, p, L);
     unsigned *ctl = ptr<unsigned>(h, L.ctl);
-    HCHK(hipMemsetAsync(ctl + CTL_PROGRESS, 0, sizeof(unsigned) * n, st));
     HCHK(kt_begin(h, SKEW_EVD_K_CHASE));
     HCHK(skew::launch_chase(ptr<double>(h, L.ab), 2 * b + 1, n, b, p.nb2, ptr<double>(h, L.V2),
                             ptr<double>(h, L.tau2), ptr<int>(h, L.goff), ctl + CTL_PROGRESS, ctl + CTL_ERR,
                             ptr<double>(h, L.alpha), st));
     HCHK(kt_end(h, SKEW_EVD_K_CHASE));
-    HCHK(hipEventRecord(h->ev[3], st));
+    HCHK(ev_record(h, 3));
+    return SKEW_EVD_OK;
+}
+
+// Gram-Schmidt windows.  Inverse iteration gives vectors accurate to about
+// eps ||T|| / gap, so vectors of eigenvalues closer than a fraction of ||T||
+// must be orthogonalized against each other.  The window of the block that
+// starts at vector b0 covers the orth_window vectors before it and, beyond
+// them, every earlier vector whose eigenvalue lies within 1e-3 ||T|| of
+// lambda_b0 (the cluster criterion of LAPACK's dstein), so a cluster of any
+// width is orthogonalized as a whole.
+//
+// Degenerate clusters (consecutive eigenvalues closer than DEGEN_TOL ||T||,
+// numerically equal) need one more step.  Their inverse-iteration vectors are
+// random within the invariant subspace, so the last blocks of a cluster that
+// fills its subspace are ill-conditioned, and orthonormalizing them magnifies
+// the small components outside the subspace (residual and orthogonality
+// errors up to ~1e-9 for clusters of 2048).  After the Gram-Schmidt pass each
+// such vector gets one inverse-iteration step with the shift lambda_c0 - d
+// (lambda_c0 the cluster's smallest value, d = max(1e-10 ||T||, 1e3 x the
+// cluster's width)): every direction inside the cluster is magnified by
+// nearly the same 1/d, so the basis stays well-conditioned, while the
+// components outside shrink by d / gap.  A second Gram-Schmidt pass from the
+// first polished block then restores orthonormality.
+constexpr double ORTH_CLUSTER = 1e-3;
+constexpr double DEGEN_TOL = 1e3 * 2.220446049250313e-16;
+
+bool windows_fixed(const Plan &p, int nev) { return nev <= p.orth_window; }
+
+// enqueue the copy of the eigenvalues and ||T|| to the host (after the bisection)
+int fetch_windows(skew_evd_handle h, const Plan &p, const Layout &L, const double *lam_dev, int nev)
+{
+    (void)p;
+    if (h->async) return SKEW_EVD_OK;
+    if (!h->win_ev) HCHK(hipEventCreateWithFlags(&h->win_ev, hipEventDisableTiming));
+    if ((size_t)2 * nev + 1 > h->lam_cap) {
+        if (h->lam_host) HCHK(hipHostFree(h->lam_host));
+        h->lam_host = nullptr;
+        h->lam_cap = 0;
+        HCHK(hipHostMalloc((void **)&h->lam_host, sizeof(double) * (2 * nev + 1), hipHostMallocDefault));
+        h->lam_cap = 2 * nev + 1;
+    }
+    HCHK(hipMemcpyAsync(h->lam_host, lam_dev, sizeof(double) * nev, hipMemcpyDeviceToHost, h->stream));
+    HCHK(hipMemcpyAsync(h->lam_host + nev, ptr<double>(h, L.stats), sizeof(double), hipMemcpyDeviceToHost,
+                        h->stream));
+    HCHK(hipEventRecord(h->win_ev, h->stream));
+    return SKEW_EVD_OK;
+}
+
+// wait for that copy (work queued after it keeps running), set the windows,
+// and find the degenerate clusters with their polishing shifts
+int plan_windows(skew_evd_handle h, const Plan &p, int nev)
+{
+    h->win0.clear();
+    h->polish_lo = h->polish_hi = 0;
+    if (h->async) return SKEW_EVD_OK;       // fixed windows; degenerate clusters are flagged on the device
+    HCHK(hipEventSynchronize(h->win_ev));
+    const double *lam = h->lam_host;
+    const double g = h->lam_host[nev];      // ||T||_inf
+    if (!windows_fixed(p, nev)) {
+        const int nblk = (nev + ORTH_NB - 1) / ORTH_NB;
+        const double tau = ORTH_CLUSTER * g;
+        for (int k = 0; k < nblk; ++k) {
+            const int b0 = k * ORTH_NB;
+            const int wfix = std::max(0, b0 - p.orth_window);
+            const int wclu = (int)(std::lower_bound(lam, lam + b0, lam[b0] - tau) - lam);
+            h->win0.push_back(std::min(wfix, wclu));
+        }
+    }
+    double *sh = h->lam_host + nev + 1;
+    int lo = -1, hi = -1;
+    for (int k = 0; k < nev;) {
+        int j = k;
+        while (j + 1 < nev && lam[j + 1] - lam[j] <= DEGEN_TOL * g) ++j;
+        if (j > k && g > 0.0) {
+            const double d = std::max(1e-10 * g, 1e3 * (lam[j] - lam[k]));
+            for (int c = k; c <= j; ++c) sh[c] = lam[k] - d;
+            if (lo < 0) lo = k;
+            hi = j + 1;
+        } else {
+            sh[k] = lam[k];
+        }
+        k = j + 1;
+    }
+    if (lo >= 0) {
+        h->polish_lo = lo;
+        h->polish_hi = hi;
+    }
     return SKEW_EVD_OK;
 }
 
 // Block Gram-Schmidt in eigenvalue order (window of earlier vectors, then a
-// Cholesky-QR of the block).
-int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, int ldq, int n, int nev)
+// Cholesky-QR of the block).  A window that a cluster extends beyond the
+// fixed length is projected out twice (classical Gram-Schmidt needs the
+// second pass when a block is nearly in the span of its window).
+int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, int ldq, int n, int nev,
+                  int first = 0)
 {
     hipStream_t st = h->stream;
-    for (int b0 = 0; b0 < nev; b0 += ORTH_NB) {
+    for (int b0 = first; b0 < nev; b0 += ORTH_NB) {
         const int nb = std::min(ORTH_NB, nev - b0);
-        const int w0 = std::max(0, b0 - p.orth_window);
+        const int w0 = h->win0.empty() ? std::max(0, b0 - p.orth_window) : h->win0[b0 / ORTH_NB];
         const int wl = b0 - w0;
+        const int passes = wl > p.orth_window ? 2 : 1;
         double *Qb = Q + (size_t)b0 * ldq;
-        if (wl > 0) {
+        for (int pass = 0; wl > 0 && pass < passes; ++pass) {
             const double *Qw = Q + (size_t)w0 * ldq;
             int S = skew::launch_gemm_tn_part<double>(Qw, ldq, Qb, ldq, wl, nb, n, ptr<double>(h, L.Pp), st);
             skew::launch_reduce_left(nullptr, ptr<double>(h, L.Pp), S, wl, nb, ptr<double>(h, L.P), st);
@@ -433,6 +544,10 @@ int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, 
 
 int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L);
 
+// Inverse iteration: a vector whose residual exceeds this multiple of ||T||
+// is reported as not converged.
+constexpr double INVIT_CTOL = 1e-12;
+
 // early_t: start the T factors of the stage-2 groups on the second stream
 // once the bisection (which fills the device) is queued, so that they run
 // beside the inverse iteration.
@@ -443,19 +558,43 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
     const int n = p.n;
     HCHK(kt_begin(h, SKEW_EVD_K_TRIDIAG));
     skew::launch_tridiag_eigvals(alpha, n, n / 2, nev, ptr<double>(h, L.a2), ptr<double>(h, L.stats), lam, st);
+    int rc = fetch_windows(h, p, L, lam, nev);
+    if (rc) return rc;
     if (early_t) {
-        int rc = start_bt2_factors(h, p, L);
+        rc = start_bt2_factors(h, p, L);
         if (rc) return rc;
     }
+    const double ctol = (h->debug & SKEW_EVD_DEBUG_INVIT_NOCONV) ? 0.0 : INVIT_CTOL;
     skew::launch_tridiag_eigvecs(alpha, n, nev, lam, ptr<double>(h, L.stats), ptr<double>(h, L.U0),
                                  ptr<double>(h, L.U1), ptr<double>(h, L.U2), ptr<double>(h, L.Lm),
                                  ptr<unsigned char>(h, L.Sw), ptr<double>(h, L.Yiv), ptr<double>(h, L.ivfac), Q,
-                                 ldq, st);
+                                 ldq, ctol, ptr<unsigned>(h, L.ctl) + CTL_ERR, st);
     HCHK(hipGetLastError());
-    int rc = orthogonalize(h, p, L, Q, ldq, n, nev);
+    rc = plan_windows(h, p, nev);
     if (rc) return rc;
+    rc = orthogonalize(h, p, L, Q, ldq, n, nev);
+    if (rc) return rc;
+    if (h->polish_hi > h->polish_lo) {
+        // degenerate clusters: one inverse-iteration step with cluster shifts,
+        // then Gram-Schmidt again from the first block they touch
+        const int lo = h->polish_lo, m = h->polish_hi - lo;
+        HCHK(hipMemcpyAsync(ptr<double>(h, L.pshift), h->lam_host + nev + 1 + lo, sizeof(double) * m,
+                            hipMemcpyHostToDevice, st));
+        skew::launch_tridiag_polish(alpha, n, m, lam + lo, ptr<double>(h, L.pshift), ptr<double>(h, L.stats),
+                                    ptr<double>(h, L.U0), ptr<double>(h, L.U1), ptr<double>(h, L.U2),
+                                    ptr<double>(h, L.Lm), ptr<unsigned char>(h, L.Sw), ptr<double>(h, L.Yiv),
+                                    ptr<double>(h, L.ivfac), Q + (size_t)lo * ldq, ldq, st);
+        HCHK(hipGetLastError());
+        rc = orthogonalize(h, p, L, Q, ldq, n, nev, (lo / ORTH_NB) * ORTH_NB);
+        if (rc) return rc;
+        // the host image of the shifts must outlive the copy
+        HCHK(hipStreamSynchronize(st));
+    } else if (h->async) {
+        skew::launch_degenerate_check(lam, nev, ptr<double>(h, L.stats), DEGEN_TOL, ptr<unsigned>(h, L.ctl) + CTL_FLAGS,
+                                      st);
+    }
     HCHK(kt_end(h, SKEW_EVD_K_TRIDIAG));
-    HCHK(hipEventRecord(h->ev[4], st));
+    HCHK(ev_record(h, 4));
     return SKEW_EVD_OK;
 }
 
@@ -554,7 +693,7 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L, bool 
         HCHK(kt_end(h, SKEW_EVD_K_BT2));
     }
     HCHK(hipGetLastError());
-    HCHK(hipEventRecord(h->ev[5], st));
+    HCHK(ev_record(h, 5));
     if (merged_bt1(p)) {
         // consecutive panels merged in pairs: Q_j Q_{j+1} = I - V T V^T with
         // V = [V_j, V_{j+1} shifted by b rows]; pairs end at the last panel
@@ -581,7 +720,7 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L, bool 
             HCHK(hipGetLastError());
         }
         HCHK(kt_end(h, SKEW_EVD_K_BT1));
-        HCHK(hipEventRecord(h->ev[6], st));
+        HCHK(ev_record(h, 6));
         return SKEW_EVD_OK;
     }
     for (int j = p.npanels - 1; j >= 0; --j) {
@@ -595,7 +734,7 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L, bool 
         HCHK(kt_end(h, SKEW_EVD_K_BT1));
         HCHK(hipGetLastError());
     }
-    HCHK(hipEventRecord(h->ev[6], st));
+    HCHK(ev_record(h, 6));
     return SKEW_EVD_OK;
 }
 
@@ -606,7 +745,12 @@ int finish_status(skew_evd_handle h, const Layout &L)
     HCHK(hipStreamSynchronize(h->stream));
     if (h->ctl_host[CTL_FLAGS] & 1u) return SKEW_EVD_ERR_NONFINITE;
     if (h->ctl_host[CTL_ERR]) {
-        snprintf(g_errtext, sizeof(g_errtext), "a device-side wait gave up (code %u)", h->ctl_host[CTL_ERR]);
+        const unsigned c = h->ctl_host[CTL_ERR];
+        if (c == 8u)
+            snprintf(g_errtext, sizeof(g_errtext), "inverse iteration left a vector with residual above %.0e ||T||",
+                     INVIT_CTOL);
+        else
+            snprintf(g_errtext, sizeof(g_errtext), "a device-side wait gave up (code %u)", c);
         return SKEW_EVD_ERR_NOCONV;
     }
     return SKEW_EVD_OK;
@@ -632,6 +776,8 @@ int validate_opts(const skew_evd_opts *o)
     if (o->precision != SKEW_EVD_PREC_FP64 && o->precision != SKEW_EVD_PREC_FP32_REFINE) return 1;
     if (o->band != 0 && !band_supported(o->band)) return 1;
     if (o->max_refine_sweeps < 0) return 1;
+    if (o->no_fp64_fallback != 0 && o->no_fp64_fallback != 1) return 1;
+    if (o->debug & ~(SKEW_EVD_DEBUG_NAN_WS | SKEW_EVD_DEBUG_ZERO_WS | SKEW_EVD_DEBUG_INVIT_NOCONV)) return 1;
     return 0;
 }
 
@@ -659,7 +805,7 @@ int refine(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, i
     h->refine_passes = 0;
     for (int sw = 0; sw < std::max(1, o.max_refine_sweeps); ++sw) {
         ++h->refine_passes;
-        HCHK(hipMemsetAsync(stat, 0, sizeof(double) * 8, st));
+        skew::launch_fill32(stat, 0u, 16, st);
         skew::launch_refine_products(A, lda, n, X, ncx, ptr<double>(h, L.rP), ptr<double>(h, L.rS),
                                      ptr<double>(h, L.rG), st);
         skew::launch_refine_eigs(ptr<double>(h, L.rS), ptr<double>(h, L.rG), ncx, nblk, odd, ptr<double>(h, L.rlam),
@@ -688,7 +834,12 @@ int refine(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, i
         memcpy(&hc, &hb[0], sizeof(unsigned));
         const double ecor = hb[1];
         if (hc) {
-            // near-degenerate pairs the FP32 start cannot separate: not refinable here
+            // near-degenerate pairs the FP32 start cannot separate: not refinable
+            // here; the outputs get the current iterate X (its eigenvalues are rlam)
+            HCHK(hipMemcpyAsync(lambda, ptr<double>(h, L.rlam), sizeof(double) * nev_out, hipMemcpyDeviceToDevice,
+                                st));
+            skew::launch_split_x(X, n, nev_out, odd, Z_re, ldzr, Z_im, ldzi, st);
+            HCHK(hipGetLastError());
             *sweeps_out = sweeps;
             *res_out = last;
             return SKEW_EVD_REFINE_CLUSTER;
@@ -727,12 +878,16 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     int rc = ensure_ws(h, L.total, o.workspace_limit);
     if (rc) return rc;
     hipStream_t st = h->stream;
+    h->debug = (unsigned)o.debug;
     kt_reset(h, o.profile != 0, o.profile == 2 ? SKEW_EVD_K_BT2 : -1);
     bool rec[NSTAGE_EV] = {};
     // work left on the second stream by an earlier call that returned early
     if (h->aux) HCHK(hipStreamWaitEvent(st, h->aux_ev[2], 0));
-    HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, st));
-    HCHK(hipEventRecord(h->ev[0], st));
+    // test hooks: every workspace byte NaN (0xff) or zero before the solve
+    if (o.debug & SKEW_EVD_DEBUG_NAN_WS) skew::launch_fill32(h->ws, 0xffffffffu, h->ws_bytes / 4, st);
+    else if (o.debug & SKEW_EVD_DEBUG_ZERO_WS) skew::launch_fill32(h->ws, 0u, h->ws_bytes / 4, st);
+    skew::launch_fill32(ptr<unsigned>(h, L.ctl), 0u, 64, st);
+    HCHK(ev_record(h, 0));
     rec[0] = true;
     rc = prec ? stage_band<float>(h, p, L, A, lda, 1) : stage_band<double>(h, p, L, A, lda, 1);
     if (rc) return rc;
@@ -753,7 +908,7 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     if (prec) {
         HCHK(kt_begin(h, SKEW_EVD_K_REFINE));
         refine_rc = refine(h, p, L, A, lda, o, nev_out, lambda, Z_re, ldzr, Z_im, ldzi, &rsweeps, &rres);
-        if (refine_rc == SKEW_EVD_REFINE_CLUSTER || refine_rc == SKEW_EVD_WARN_REFINE) {
+        if ((refine_rc == SKEW_EVD_REFINE_CLUSTER || refine_rc == SKEW_EVD_WARN_REFINE) && !o.no_fp64_fallback) {
             // clusters closer than the FP32 pipeline resolves, or no convergence
             // within max_refine_sweeps: fall back to the FP64 form
             skew_evd_opts o64 = o;
@@ -762,10 +917,11 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
             if (info) info->refine_sweeps = -1;   // marks the fallback
             return rc64;
         }
+        if (refine_rc == SKEW_EVD_REFINE_CLUSTER) refine_rc = SKEW_EVD_WARN_REFINE;
         if (refine_rc != SKEW_EVD_OK && refine_rc != SKEW_EVD_WARN_REFINE) return refine_rc;
         HCHK(kt_end(h, SKEW_EVD_K_REFINE));
     }
-    HCHK(hipEventRecord(h->ev[7], st));
+    HCHK(ev_record(h, 7));
     rec[7] = true;
     if (!prec) {
         HCHK(hipMemcpyAsync(lambda, ptr<double>(h, L.lam), sizeof(double) * nev, hipMemcpyDeviceToDevice, st));
@@ -775,7 +931,7 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
         HCHK(hipMemcpy2DAsync(Z_im, sizeof(double) * ldzi, Z + (size_t)nev * n, sizeof(double) * n,
                               sizeof(double) * n, nev, hipMemcpyDeviceToDevice, st));
     }
-    HCHK(hipEventRecord(h->ev[8], st));
+    HCHK(ev_record(h, 8));
     rec[8] = true;
     rc = finish_status(h, L);
     if (rc == SKEW_EVD_OK) rc = refine_rc;
@@ -848,7 +1004,8 @@ int skew_evd_destroy(skew_evd_handle h)
     for (int i = 0; i < NSTAGE_EV; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->ctl_host) (void)hipHostFree(h->ctl_host);
-    if (h->goff_host) (void)hipHostFree(h->goff_host);
+    if (h->lam_host) (void)hipHostFree(h->lam_host);
+    if (h->win_ev) (void)hipEventDestroy(h->win_ev);
     for (auto e : h->kev) (void)hipEventDestroy(e);
     if (h->aux) {
         (void)hipStreamSynchronize(h->aux);
@@ -856,8 +1013,13 @@ int skew_evd_destroy(skew_evd_handle h)
     }
     for (auto e : h->aux_ev)
         if (e) (void)hipEventDestroy(e);
-    for (auto sh : h->sub) skew_evd_destroy(sh);
-    for (auto s2 : h->sub_streams) (void)hipStreamDestroy(s2);
+    for (auto s2 : h->sub_streams) {
+        (void)hipStreamSynchronize(s2);
+        (void)hipStreamDestroy(s2);
+    }
+    for (auto e : h->bev) (void)hipEventDestroy(e);
+    if (h->bev0) (void)hipEventDestroy(h->bev0);
+    if (h->bhost) (void)hipHostFree(h->bhost);
     delete h;
     return SKEW_EVD_OK;
 }
@@ -1043,6 +1205,249 @@ int skew_evd(int n, const double *A, int lda, int nev, double *lambda, double *Z
     return skew_evd_ex(h, n, A, lda, nev, lambda, Z_re, n, Z_im, n, nullptr, nullptr);
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Batched form.  Problems up to BATCH_NMAX are solved together, each in its
+// own slice of one batch workspace held by the handle:
+//   A. on BATCH_STREAMS sub-streams (problems dealt largest first to the
+//      least-loaded stream, work ~ n^3): ingest, full-to-band reduction and
+//      the chase's preparation;
+//   B. one bulge-chase launch for every band: the problems are dealt to up to
+//      CHASE_LANES lanes (largest first to the lane with the fewest sweeps)
+//      and chased side by side;
+//   C. on the sub-streams again: tridiagonal solve, D and both
+//      back-transformations, copy-out, and the problem's two status words
+//      into a device array.
+// No step waits on the host; one synchronisation ends the call.  The orders
+// above BATCH_NMAX (whose Gram-Schmidt windows need their eigenvalues on the
+// host), and the problems whose spectrum holds a degenerate cluster (their
+// eigenvectors need the polishing step, planned on the host), are solved one
+// by one afterwards.
+constexpr int BATCH_NMAX = 4096;
+constexpr int BATCH_STREAMS = 8;
+constexpr int CHASE_LANES = 64;
+
+struct BatchItem {
+    int idx;
+    Plan p;
+    Layout L;
+    size_t off;
+};
+
+// a view of the batch workspace slice of one problem, on a sub-stream
+skew_evd_handle_s *make_view(skew_evd_handle h, const BatchItem &it, hipStream_t st)
+{
+    skew_evd_handle_s *v = new skew_evd_handle_s();
+    v->stream = st;
+    v->device = h->device;
+    v->ws = h->ws + it.off;
+    v->ws_bytes = it.L.total;
+    v->async = true;
+    return v;
+}
+
+int batch_part_a(skew_evd_handle v, const BatchItem &it, const double *A, int lda)
+{
+    skew::launch_fill32(ptr<unsigned>(v, it.L.ctl), 0u, 64, v->stream);
+    int rc = stage_band<double>(v, it.p, it.L, A, lda, 1);
+    if (rc) return rc;
+    chase_prepare(v, it.p, it.L);
+    HCHK(hipGetLastError());
+    return SKEW_EVD_OK;
+}
+
+int batch_part_c(skew_evd_handle v, const BatchItem &it, double *lambda, double *Z_re, double *Z_im,
+                 unsigned *stat)
+{
+    const Plan &p = it.p;
+    const Layout &L = it.L;
+    const int n = p.n, nev = p.nev;
+    hipStream_t st = v->stream;
+    skew::launch_alpha(ptr<double>(v, L.ab), 2 * p.b + 1, n, ptr<double>(v, L.alpha), st);
+    if (n == 1) skew::launch_fill32(ptr<double>(v, L.alpha), 0u, 2, st);
+    int rc = stage_tridiag(v, p, L, ptr<double>(v, L.alpha), nev, ptr<double>(v, L.lam), ptr<double>(v, L.Qd), n,
+                           false);
+    if (rc) return rc;
+    rc = stage_backtransform<double>(v, p, L, false);
+    if (rc) return rc;
+    HCHK(hipMemcpyAsync(lambda, ptr<double>(v, L.lam), sizeof(double) * nev, hipMemcpyDeviceToDevice, st));
+    const double *Z = ptr<double>(v, L.Z);
+    HCHK(hipMemcpyAsync(Z_re, Z, sizeof(double) * n * nev, hipMemcpyDeviceToDevice, st));
+    HCHK(hipMemcpyAsync(Z_im, Z + (size_t)nev * n, sizeof(double) * n * nev, hipMemcpyDeviceToDevice, st));
+    HCHK(hipMemcpyAsync(stat, ptr<unsigned>(v, L.ctl), sizeof(unsigned) * 2, hipMemcpyDeviceToDevice, st));
+    return SKEW_EVD_OK;
+}
+
+int ensure_streams(skew_evd_handle h, int S)
+{
+    while ((int)h->sub_streams.size() < S) {
+        hipStream_t s2;
+        HCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        h->sub_streams.push_back(s2);
+        hipEvent_t e;
+        HCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->bev.push_back(e);
+    }
+    if (!h->bev0) HCHK(hipEventCreateWithFlags(&h->bev0, hipEventDisableTiming));
+    return SKEW_EVD_OK;
+}
+
+// the sub-streams 0..S-1 wait for the work queued on h->stream
+int fork_streams(skew_evd_handle h, int S)
+{
+    HCHK(hipEventRecord(h->bev0, h->stream));
+    for (int k = 0; k < S; ++k) HCHK(hipStreamWaitEvent(h->sub_streams[k], h->bev0, 0));
+    return SKEW_EVD_OK;
+}
+
+// h->stream waits for the work queued on the sub-streams 0..S-1
+int join_streams(skew_evd_handle h, int S)
+{
+    for (int k = 0; k < S; ++k) {
+        HCHK(hipEventRecord(h->bev[k], h->sub_streams[k]));
+        HCHK(hipStreamWaitEvent(h->stream, h->bev[k], 0));
+    }
+    return SKEW_EVD_OK;
+}
+
+// Problems whose spectrum holds a degenerate cluster (flagged on the device)
+// are appended to `again`, to be solved on their own.
+int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *n, const double *const *A,
+                     const int *lda, const int *nev, double *const *lambda, double *const *Z_re,
+                     double *const *Z_im, const std::vector<skew_evd_opts> &popt, size_t wslimit, int *status,
+                     std::vector<int> &again)
+{
+    const int cnt = (int)ids.size();
+    if (cnt == 0) return SKEW_EVD_OK;
+    std::vector<BatchItem> it(cnt);
+    size_t off = 0;
+    for (int k = 0; k < cnt; ++k) {
+        const int i = ids[k];
+        it[k].idx = i;
+        it[k].p = make_plan(n[i], nev[i], popt[i].band, 0);
+        it[k].L = plan_layout(it[k].p);
+        it[k].off = off;
+        off += it[k].L.total;
+    }
+    const int M = std::min(cnt, CHASE_LANES);
+    const size_t probs_off = off;
+    off += al(sizeof(skew::ChaseProb) * cnt);
+    const size_t lanes_off = off;
+    off += al(sizeof(int) * (M + 1 + 2 * cnt));
+    const size_t stat_off = off;
+    off += al(sizeof(unsigned) * (2 * cnt + 2));
+    int rc = ensure_ws(h, off, wslimit);
+    if (rc) return rc;
+    const int S = std::min(cnt, BATCH_STREAMS);
+    rc = ensure_streams(h, S);
+    if (rc) return rc;
+    // streams (LPT on n^3) and chase lanes (LPT on sweeps)
+    std::vector<int> order(cnt);
+    for (int k = 0; k < cnt; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return it[a].p.n > it[b].p.n; });
+    std::vector<std::vector<int>> part(S), lane(M);
+    std::vector<double> load(S, 0.0);
+    std::vector<long> lload(M, 0);
+    for (int k : order) {
+        const int s2 = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        part[s2].push_back(k);
+        const double nn = it[k].p.n;
+        load[s2] += nn * nn * nn + 1e6;
+        const int l = (int)(std::min_element(lload.begin(), lload.end()) - lload.begin());
+        lane[l].push_back(k);
+        lload[l] += std::max(it[k].p.n - 2, 0);
+    }
+    // host images of the chase descriptors, then one copy to the device
+    const size_t hbytes = sizeof(skew::ChaseProb) * cnt + sizeof(int) * (M + 1 + 2 * cnt) +
+                          sizeof(unsigned) * (2 * cnt + 2);
+    if (hbytes > h->bhost_cap) {
+        if (h->bhost) HCHK(hipHostFree(h->bhost));
+        h->bhost = nullptr;
+        h->bhost_cap = 0;
+        HCHK(hipHostMalloc((void **)&h->bhost, hbytes, hipHostMallocDefault));
+        h->bhost_cap = hbytes;
+    }
+    skew::ChaseProb *hp = (skew::ChaseProb *)h->bhost;
+    int *hl = (int *)(hp + cnt);
+    unsigned *hs = (unsigned *)(hl + M + 1 + 2 * cnt);
+    int maxlen = 0, nitem = 0;
+    for (int l = 0; l < M; ++l) {
+        hl[l] = nitem;
+        int pos = 0;
+        for (int k : lane[l]) {
+            hl[M + 1 + 2 * nitem] = k;
+            hl[M + 1 + 2 * nitem + 1] = pos;
+            ++nitem;
+            pos += std::max(it[k].p.n - 2, 0);
+        }
+        maxlen = std::max(maxlen, pos);
+    }
+    hl[M] = nitem;
+    for (int k = 0; k < cnt; ++k) {
+        const Plan &p = it[k].p;
+        const Layout &L = it[k].L;
+        char *w = h->ws + it[k].off;
+        unsigned *ctl = (unsigned *)(w + L.ctl);
+        hp[k] = skew::ChaseProb{(double *)(w + L.ab), (double *)(w + L.V2), (double *)(w + L.tau2),
+                                (const int *)(w + L.goff), ctl + CTL_PROGRESS, ctl + CTL_ERR, 2 * p.b + 1, p.n,
+                                p.b, p.nb2};
+    }
+    skew::ChaseProb *dprobs = (skew::ChaseProb *)(h->ws + probs_off);
+    int *dlanes = (int *)(h->ws + lanes_off);
+    unsigned *dstat = (unsigned *)(h->ws + stat_off);
+    HCHK(hipMemcpyAsync(dprobs, hp, sizeof(skew::ChaseProb) * cnt, hipMemcpyHostToDevice, h->stream));
+    HCHK(hipMemcpyAsync(dlanes, hl, sizeof(int) * (M + 1 + 2 * cnt), hipMemcpyHostToDevice, h->stream));
+    skew::launch_fill32(dstat, 0u, 2 * (size_t)cnt + 2, h->stream);
+    std::vector<skew_evd_handle_s *> views(cnt);
+    for (int s2 = 0; s2 < S; ++s2)
+        for (int k : part[s2]) views[k] = make_view(h, it[k], h->sub_streams[s2]);
+    std::vector<int> src(S, SKEW_EVD_OK);
+    auto run_parts = [&](bool first) {
+        std::vector<std::thread> workers;
+        for (int s2 = 0; s2 < S; ++s2)
+            workers.emplace_back([&, s2]() {
+                for (int k : part[s2]) {
+                    if (src[s2]) return;
+                    const int i = it[k].idx;
+                    src[s2] = first ? batch_part_a(views[k], it[k], A[i], lda[i])
+                                    : batch_part_c(views[k], it[k], lambda[i], Z_re[i], Z_im[i], dstat + 2 * k);
+                }
+            });
+        for (auto &w : workers) w.join();
+    };
+    rc = fork_streams(h, S);
+    if (!rc) {
+        run_parts(true);
+        rc = join_streams(h, S);
+    }
+    for (int s2 = 0; s2 < S && !rc; ++s2) rc = src[s2];
+    if (!rc) {
+        const int G = std::max(1, std::min(skew::chase_max_workgroups(), 8 * M));
+        HCHK(skew::launch_chase_batched(dprobs, dlanes, M, maxlen, G, dstat + 2 * cnt, h->stream));
+        rc = fork_streams(h, S);
+    }
+    if (!rc) {
+        run_parts(false);
+        rc = join_streams(h, S);
+    }
+    for (int s2 = 0; s2 < S && !rc; ++s2) rc = src[s2];
+    for (auto v : views) delete v;
+    if (!rc) HCHK(hipMemcpyAsync(hs, dstat, sizeof(unsigned) * 2 * cnt, hipMemcpyDeviceToHost, h->stream));
+    HCHK(hipStreamSynchronize(h->stream));
+    if (rc) return rc;
+    for (int k = 0; k < cnt; ++k) {
+        const int i = it[k].idx;
+        if (hs[2 * k] & 1u) status[i] = SKEW_EVD_ERR_NONFINITE;
+        else if (hs[2 * k + 1]) status[i] = SKEW_EVD_ERR_NOCONV;
+        else status[i] = SKEW_EVD_OK;
+        if (status[i] == SKEW_EVD_OK && (hs[2 * k] & 2u)) again.push_back(i);
+    }
+    return SKEW_EVD_OK;
+}
+
+}  // namespace
+
 int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *const *A, const int *lda,
                      const int *nev, double *const *lambda, double *const *Z_re, double *const *Z_im,
                      const skew_evd_opts *opts, skew_evd_info *info, int *status)
@@ -1060,31 +1465,21 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
         return -12;
     }
     if (validate_opts(opts)) return -10;
+    // the precision form is not available in the batched form (see the header)
+    if (opts && opts->precision != SKEW_EVD_PREC_FP64) return -10;
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 0) return -3;
+        if (n[i] > 0 && !A[i]) return -4;
+        if (lda[i] < std::max(1, n[i])) return -5;
+        if (nev[i] < 0 || nev[i] > (n[i] + 1) / 2) return -6;
+        if (nev[i] > 0 && !lambda[i]) return -7;
+        if (nev[i] > 0 && !Z_re[i]) return -8;
+        if (nev[i] > 0 && !Z_im[i]) return -9;
+    }
     if (info) memset(info, 0, sizeof(*info));
     if (count == 0) return SKEW_EVD_OK;
-    // Problems are dealt to NS sub-handles (own stream and workspace), largest
-    // first to the least-loaded one (longest-processing-time rule, work ~ n^3);
-    // each sub-handle is driven by its own host thread, so the small solves
-    // overlap on the device.
-    // concurrent streams only for small problems: their cooperative launches
-    // (at most (n/b)/3 + 16 workgroups each) then fit on the device together
-    int nmax = 0;
-    for (int i = 0; i < count; ++i) nmax = std::max(nmax, n[i]);
-    const int NS = nmax <= 2048 ? std::min(count, 8) : 1;
-    while ((int)h->sub.size() < NS) {
-        hipStream_t s2;
-        HCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
-        skew_evd_handle sh = nullptr;
-        int rc = skew_evd_create(&sh, (void *)s2);
-        if (rc) {
-            (void)hipStreamDestroy(s2);
-            return rc;
-        }
-        h->sub.push_back(sh);
-        h->sub_streams.push_back(s2);
-    }
-    // autotuned band widths: each size class is tuned once on h, before the
-    // problems are dealt out; the sub-handles then solve with a fixed band
+    // autotuned band widths: each size class is tuned once on h, before any
+    // problem is solved
     std::vector<skew_evd_opts> popt(count);
     for (int i = 0; i < count; ++i) {
         if (opts) popt[i] = *opts;
@@ -1101,50 +1496,32 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
         }
         popt[i].autotune = 0;
     }
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
-    std::vector<std::vector<int>> part(NS);
-    std::vector<double> load(NS, 0.0);
-    for (int i : order) {
-        int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        part[best].push_back(i);
-        load[best] += (double)n[i] * n[i] * n[i] + 1e6;
+    const size_t wslimit = opts ? opts->workspace_limit : 0;
+    std::vector<int> together, alone;
+    for (int i = 0; i < count; ++i) {
+        status[i] = SKEW_EVD_OK;
+        if (n[i] == 0 || nev[i] == 0) continue;
+        (n[i] <= BATCH_NMAX ? together : alone).push_back(i);
     }
-    // the sub-streams start after the work already queued on h->stream
-    hipEvent_t start;
-    HCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-    HCHK(hipEventRecord(start, h->stream));
-    for (int s2 = 0; s2 < NS; ++s2) HCHK(hipStreamWaitEvent(h->sub_streams[s2], start, 0));
-    std::vector<skew_evd_info> sinfo(NS);
-    std::vector<std::thread> workers;
-    for (int s2 = 0; s2 < NS; ++s2) {
-        workers.emplace_back([&, s2]() {
-            memset(&sinfo[s2], 0, sizeof(skew_evd_info));
-            for (int i : part[s2]) {
-                skew_evd_info one;
-                status[i] = skew_evd_ex(h->sub[s2], n[i], A[i], lda[i], nev[i], lambda[i], Z_re[i], std::max(1, n[i]),
-                                        Z_im[i], std::max(1, n[i]), &popt[i], &one);
-                sinfo[s2].ms_total += one.ms_total;
-                for (int k = 0; k < 8; ++k) sinfo[s2].ms_stage[k] += one.ms_stage[k];
-                sinfo[s2].band = one.band;
-            }
-        });
+    HCHK(hipEventRecord(h->ev[0], h->stream));
+    int rc = batched_together(h, together, n, A, lda, nev, lambda, Z_re, Z_im, popt, wslimit, status, alone);
+    if (rc) {
+        for (int i : together) status[i] = rc;
+        return rc;
     }
-    for (auto &w : workers) w.join();
-    (void)hipEventDestroy(start);
+    for (int i : alone)
+        status[i] = skew_evd_ex(h, n[i], A[i], lda[i], nev[i], lambda[i], Z_re[i], std::max(1, n[i]), Z_im[i],
+                                std::max(1, n[i]), &popt[i], nullptr);
+    HCHK(hipEventRecord(h->ev[8], h->stream));
+    HCHK(hipEventSynchronize(h->ev[8]));
     int first = 0;
     for (int i = 0; i < count; ++i)
         if (status[i] && !first) first = status[i];
     if (info) {
-        for (int s2 = 0; s2 < NS; ++s2) {
-            info->ms_total = std::max(info->ms_total, sinfo[s2].ms_total);
-            for (int k = 0; k < 8; ++k) info->ms_stage[k] += sinfo[s2].ms_stage[k];
-        }
-        size_t ws = 0;
-        for (auto sh : h->sub) ws += sh->ws_bytes;
-        info->workspace_bytes = ws;
-        info->band = sinfo[0].band;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev[0], h->ev[8]) == hipSuccess) info->ms_total = ms;
+        info->workspace_bytes = h->ws_bytes;
+        info->band = together.empty() ? 0 : make_plan(n[together[0]], nev[together[0]], popt[together[0]].band, 0).b;
     }
     return first;
 }
@@ -1164,7 +1541,7 @@ int skew_evd_band_reduce(skew_evd_handle h, int n, const double *A, int lda, int
     kt_reset(h, false);
     int rc = ensure_ws(h, L.total, 0);
     if (rc) return rc;
-    HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, h->stream));
+    skew::launch_fill32(ptr<unsigned>(h, L.ctl), 0u, 64, h->stream);
     HCHK(hipEventRecord(h->ev[0], h->stream));
     rc = stage_band<double>(h, p, L, A, lda, 1);
     if (rc) return rc;
@@ -1187,7 +1564,7 @@ int skew_evd_tridiagonalize(skew_evd_handle h, int n, const double *A, int lda, 
     kt_reset(h, false);
     int rc = ensure_ws(h, L.total, 0);
     if (rc) return rc;
-    HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, h->stream));
+    skew::launch_fill32(ptr<unsigned>(h, L.ctl), 0u, 64, h->stream);
     HCHK(hipEventRecord(h->ev[0], h->stream));
     rc = stage_band<double>(h, p, L, A, lda, 1);
     if (rc) return rc;
@@ -1216,9 +1593,9 @@ int skew_evd_tridiag_eig(skew_evd_handle h, int n, const double *alpha, int nev,
     kt_reset(h, false);
     int rc = ensure_ws(h, L.total, 0);
     if (rc) return rc;
-    HCHK(hipMemsetAsync(ptr<unsigned>(h, L.ctl), 0, sizeof(unsigned) * 64, h->stream));
+    skew::launch_fill32(ptr<unsigned>(h, L.ctl), 0u, 64, h->stream);
     if (n == 1) {
-        HCHK(hipMemsetAsync(ptr<double>(h, L.alpha), 0, sizeof(double), h->stream));
+        skew::launch_fill32(ptr<double>(h, L.alpha), 0u, 2, h->stream);
         alpha = ptr<double>(h, L.alpha);
     }
     rc = stage_tridiag(h, p, L, alpha, nev, lambda, Q, ldq);

@@ -782,13 +782,13 @@ __global__ __launch_bounds__(256) void k_reduce_left(const double *__restrict__ 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int u = u0 + threadIdx.x + 256 * q;
-            if (u < M) cs[u] = acc[q];
+            if (u < M) {
+                if (S0) cs[u] = acc[q];
+                else out[(size_t)j * M + u] = acc[q];   // plain sum: no LDS needed (any M)
+            }
         }
     }
-    if (!S0) {
-        for (int u = threadIdx.x; u < M; u += 256) out[(size_t)j * M + u] = cs[u];
-        return;
-    }
+    if (!S0) return;
     double *Ss = cs + M;
     for (int e = threadIdx.x; e < M * M; e += 256) Ss[e] = S0[e];
     __syncthreads();
@@ -904,7 +904,7 @@ void launch_gemm_nn(const T *A, int lda, const double *Bpart, int S, int M, int 
 void launch_reduce_left(const double *S0, const double *Cpart, int S, int M, int N, double *out, hipStream_t st)
 {
     if (M <= 0 || N <= 0) return;
-    size_t shm = sizeof(double) * ((size_t)M + (S0 ? (size_t)M * M : 0));
+    size_t shm = S0 ? sizeof(double) * ((size_t)M + (size_t)M * M) : 0;
     hipLaunchKernelGGL(k_reduce_left, dim3(N), dim3(256), shm, st, S0, Cpart, S, M, N, out);
 }
 

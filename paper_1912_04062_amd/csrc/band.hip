@@ -11,7 +11,8 @@
 // Kernels:
 //   k_ingest      copy the strict lower triangle of A into the work matrix,
 //                 flagging non-finite entries
-//   k_panel_qr    Householder QR of one panel, cooperative (grid barriers),
+//   k_panel_qr    Householder QR of one panel (grid barriers; its few workgroups
+//                 are resident together),
 //                 rows resident in LDS, FP64 norms and dot products; also
 //                 accumulates T column by column
 //   k_skew_symm   Y0 = A V (split-K partials), A read from the lower triangle
@@ -541,11 +542,13 @@ __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__rest
 // R_h = S R into the panel's top block of W (upper triangle), U^{-1} into
 // cq[CQ_UINV].  Nothing is done when the flag is set.  Two workgroups: both
 // factor the top block (the same deterministic steps, so the same L, U and
-// S), then workgroup 0 inverts U and writes L, U^{-1} and R_h while
-// workgroup 1 forms T and tau.  L overwrites the input block, so workgroup 1
-// sets *hand once it holds its copy of the input and workgroup 0 waits for
+// S), then workgroup 1 inverts U and writes L, U^{-1} and R_h while
+// workgroup 0 forms T and tau.  L overwrites the input block, so workgroup 0
+// sets *hand once it holds its copy of the input and workgroup 1 waits for
 // that (bounded; code 4 in *err) before writing, then clears *hand for the
-// next launch.
+// next launch.  The waiting workgroup is the later one: workgroups start in
+// order, so the one it waits for is already running even when the device is
+// shared with other work.
 template <typename T>
 __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, int B, T *__restrict__ Wp,
                                                     int ldw, double *__restrict__ cq, double *__restrict__ Tf,
@@ -565,10 +568,10 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, i
     }
     if (tid < 64) sgn[tid] = 0.0;
     __syncthreads();
-    if (blockIdx.x == 1 && tid == 0) st_relaxed(hand, 1u);   // the input is in LDS
+    if (blockIdx.x == 0 && tid == 0) st_relaxed(hand, 1u);   // the input is in LDS
     lu_signed64(M, B, sgn);
     const double *R = cq + CQ_R * BB;
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 1) {
         tri_inv_upper(M, X, B, part, rinv);        // X = U^{-1}
         if (tid == 0) {
             unsigned spins = 0;
@@ -610,7 +613,7 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, i
             Ts[tx * 65 + c] = -M[tx * 65 + c] * sgn[c] - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx]);
         __syncthreads();
     }
-    // outputs of workgroup 1: T, tau
+    // outputs of workgroup 0: T, tau
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int c = ty + 4 * q, r = tx;
@@ -621,11 +624,28 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, i
     }
 }
 
+
+
+// 32-bit fill (clears control words and buffers; a kernel rather than a
+// runtime memset so that the same sequence can be captured in a graph)
+__global__ void k_fill32(unsigned *__restrict__ p, unsigned v, size_t nw)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (size_t)gridDim.x * 256) p[i] = v;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Host launchers
 namespace skew {
+
+void launch_fill32(void *p, unsigned v, size_t nwords, hipStream_t st)
+{
+    if (nwords == 0) return;
+    size_t g = (nwords + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill32, dim3((unsigned)g), dim3(256), 0, st, (unsigned *)p, v, nwords);
+}
 
 template <typename T>
 void launch_ingest(const double *A, int lda, int n, T *W, int ldw, unsigned *flags, hipStream_t st)
@@ -651,8 +671,12 @@ static hipError_t panel_qr_b(T *W, int ldw, int c0, int r0, int m, T *Vd, double
                             (int)shm);
         attr = true;
     }
-    void *args[] = {&W, &ldw, &c0, &r0, &m, &Vd, &tau, &Tf, &part, &bar, &bar_base, &err, &skip};
-    return hipLaunchCooperativeKernel((const void *)k_panel_qr<T, B>, dim3(G), dim3(256), args, shm, st);
+    // an ordinary launch: at most m / 128 workgroups of one per CU, launched in
+    // stream order after the panel's producers, so they are resident together;
+    // the grid barriers are bounded all the same (code 1 in *err)
+    hipLaunchKernelGGL((k_panel_qr<T, B>), dim3(G), dim3(256), shm, st, W, ldw, c0, r0, m, Vd, tau, Tf, part, bar,
+                       bar_base, err, skip);
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -28,8 +28,14 @@
 // by the completion of step k+1.  The per-sweep counter progress[s] holds
 // 2*(steps completed) + 1 (the next step's beta is then in memory too), and
 // 2*nsteps + 1 when the sweep is done; a waiting step needs
-// min(2k + 5, 2 nsteps(s) + 1).  Sweeps are dealt round-robin to the
-// workgroups of a cooperative launch and every wait is bounded.
+// min(2k + 5, 2 nsteps(s) + 1).  Every wait is bounded.
+//
+// Sweeps are handed out in ascending order by an atomic ticket: a workgroup
+// takes the next sweep when it has finished its previous one.  A sweep only
+// waits for the sweep before it, which a running workgroup took earlier, so
+// the chain always moves whether or not every workgroup of the launch is
+// resident at once (no cooperative launch is needed, and the kernel can share
+// the device with other streams' work).
 //
 // Each reflector is written, for the back-transformation, into the group of
 // nb2 consecutive sweeps at the same step k: V2[g][col][0..b) with
@@ -54,11 +60,16 @@ __device__ __forceinline__ int nsteps_of(int n, int b, int s) { return 1 + (n - 
 // Thread (tx, ty) = (tid % 64, tid / 64) owns row tx and columns ty + 4q
 // (q = 0..15) of the 64 x 64 blocks, so every global access of a wavefront is
 // one contiguous run of a band column and no index needs a division.
-__global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, int ldab, int n, int b,
-                                                     int nb2, double *__restrict__ V2,
-                                                     double *__restrict__ tau2,
-                                                     const int *__restrict__ goff,
-                                                     unsigned *progress, unsigned *err)
+//
+// One launch chases one band (lanes = null: ticket t is sweep t of `one`) or
+// a batch of bands: the problems are dealt to M lanes, each lane a list of
+// problems whose sweeps follow each other, and ticket t is position t / M of
+// lane t % M.  A sweep waits only for the previous sweep of its own problem,
+// whose ticket is smaller, so the same progress argument holds, and M
+// problems advance side by side.
+__global__ __launch_bounds__(256) void k_bulge_chase(skew::ChaseProb one, const skew::ChaseProb *__restrict__ probs,
+                                                     const int *__restrict__ lanes, int M, int maxlen,
+                                                     unsigned *ticket)
 {
     __shared__ double vv[2][64], wv[64], dots[64], y2[64];
     __shared__ double pw[4][64], py[4][64], pd[4][64];
@@ -66,7 +77,7 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
     __shared__ double junk[64];
     __shared__ double bw[2][64 * CH_LD];
     __shared__ double tau_s[2];
-    __shared__ int abort_flag;
+    __shared__ int abort_flag, s_next, p_next;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     if (tid == 0) abort_flag = 0;
     __syncthreads();
@@ -89,7 +100,43 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
         return beta;
     };
 
-    for (int s = blockIdx.x; s < n - 2; s += gridDim.x) {
+    for (;;) {
+        __syncthreads();                          // every thread has read the previous ticket
+        if (tid == 0) {
+            const int t = (int)atomicAdd(ticket, 1u);
+            if (!lanes) {
+                s_next = t;
+                p_next = (t < one.n - 2) ? -1 : -2;
+            } else if (t >= M * maxlen) {
+                p_next = -2;                      // every lane is exhausted
+            } else {
+                // lanes: [M + 1] item ranges, then items (problem, first position)
+                const int l = t % M, pos = t / M;
+                const int i0 = lanes[l], i1 = lanes[l + 1];
+                const int *it = lanes + M + 1;
+                int p = -3, s0 = 0;
+                for (int i = i0; i < i1; ++i) {
+                    const int q = it[2 * i], first = it[2 * i + 1];
+                    if (pos >= first && pos < first + max(probs[q].n - 2, 0)) {
+                        p = q;
+                        s0 = first;
+                    }
+                }
+                p_next = p;                       // -3: past the end of this lane
+                s_next = pos - s0;
+            }
+        }
+        __syncthreads();
+        if (p_next == -2) break;
+        if (p_next == -3) continue;
+        const int s = s_next;
+        const skew::ChaseProb P = (p_next >= 0) ? probs[p_next] : one;
+        double *__restrict__ ab = P.ab;
+        double *__restrict__ V2 = P.V2;
+        double *__restrict__ tau2 = P.tau2;
+        const int *__restrict__ goff = P.goff;
+        unsigned *progress = P.progress, *err = P.err;
+        const int ldab = P.ldab, n = P.n, b = P.b, nb2 = P.nb2;
         const int nst = nsteps_of(n, b, s);
         const int nprev = (s > 0) ? nsteps_of(n, b, s - 1) : 0;
         const int sig = s / nb2, col = s % nb2;
@@ -283,6 +330,21 @@ __global__ __launch_bounds__(256) void k_bulge_chase(double *__restrict__ ab, in
     }
 }
 
+// goff[sg] for sg = 0..nsig (the same count as chase_ngroups): one thread
+__global__ void k_goff(int n, int b, int nb2, int *__restrict__ goff)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int nsw = n - 2;
+    if (nsw <= 0) return;
+    const int nsig = (nsw + nb2 - 1) / nb2;
+    int tot = 0;
+    for (int sg = 0; sg < nsig; ++sg) {
+        goff[sg] = tot;
+        tot += 1 + (n - 2 - sg * nb2) / b;
+    }
+    goff[nsig] = tot;
+}
+
 __global__ void k_alpha(const double *__restrict__ ab, int ldab, int n, double *__restrict__ alpha)
 {
     int j = blockIdx.x * 256 + threadIdx.x;
@@ -307,9 +369,9 @@ int chase_ngroups(int n, int b, int nb2, int *goff_host)
     return tot;
 }
 
-// Workgroups of the cooperative bulge-chase launch: enough for the sweeps
-// that can be in flight at once (a sweep of n/b steps starts about every
-// second step of its predecessor), never more than the device holds.
+// Workgroups of the bulge-chase launch: enough for the sweeps that can be in
+// flight at once (a sweep of n/b steps starts about every second step of its
+// predecessor), never more than the device holds.
 int chase_workgroups(int n, int b)
 {
     int dev = 0, ncu = 256;
@@ -326,17 +388,46 @@ int chase_workgroups(int n, int b)
     return G;
 }
 
+// progress: n - 2 counters and the ticket after them, all zero on entry.
 hipError_t launch_chase(double *ab, int ldab, int n, int b, int nb2, double *V2, double *tau2,
                         const int *goff, unsigned *progress, unsigned *err, double *alpha, hipStream_t st)
 {
     if (n >= 3) {
         int G = chase_workgroups(n, b);
-        void *args[] = {&ab, &ldab, &n, &b, &nb2, &V2, &tau2, &goff, &progress, &err};
-        hipError_t e = hipLaunchCooperativeKernel((const void *)k_bulge_chase, dim3(G), dim3(256), args, 0, st);
-        if (e != hipSuccess) return e;
+        ChaseProb one{ab, V2, tau2, goff, progress, err, ldab, n, b, nb2};
+        hipLaunchKernelGGL(k_bulge_chase, dim3(G), dim3(256), 0, st, one, (const ChaseProb *)nullptr,
+                           (const int *)nullptr, 0, 0, progress + (n - 2));
     }
     if (n >= 2) hipLaunchKernelGGL(k_alpha, dim3(cdiv(n, 256)), dim3(256), 0, st, (const double *)ab, ldab, n, alpha);
     return hipGetLastError();
+}
+
+hipError_t launch_chase_batched(const ChaseProb *probs, const int *lanes, int M, int maxlen, int G,
+                                unsigned *ticket, hipStream_t st)
+{
+    if (M <= 0 || maxlen <= 0) return hipSuccess;
+    ChaseProb none{};
+    hipLaunchKernelGGL(k_bulge_chase, dim3(G), dim3(256), 0, st, none, probs, lanes, M, maxlen, ticket);
+    return hipGetLastError();
+}
+
+void launch_goff(int n, int b, int nb2, int *goff, hipStream_t st)
+{
+    if (n >= 3) hipLaunchKernelGGL(k_goff, dim3(1), dim3(64), 0, st, n, b, nb2, goff);
+}
+
+void launch_alpha(const double *ab, int ldab, int n, double *alpha, hipStream_t st)
+{
+    if (n >= 2) hipLaunchKernelGGL(k_alpha, dim3(cdiv(n, 256)), dim3(256), 0, st, ab, ldab, n, alpha);
+}
+
+int chase_max_workgroups()
+{
+    int dev = 0, ncu = 256, occ = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_bulge_chase, 256, 0);
+    return ncu * (occ < 1 ? 1 : occ);
 }
 
 }  // namespace skew

@@ -108,7 +108,7 @@ __device__ __forceinline__ bool grid_sync_coh(unsigned *ctr, unsigned target, un
     return gs_ok != 0;
 }
 
-// Grid-wide barrier for cooperatively launched kernels: a monotonic counter
+// Grid-wide barrier for kernels whose workgroups are resident together: a monotonic counter
 // that every workgroup increments once per barrier; `target` is the count at
 // which this barrier opens.  Returns false when the wait gave up.
 __device__ __forceinline__ bool grid_sync(unsigned *ctr, unsigned target, unsigned *err)

@@ -7,6 +7,7 @@
 namespace skew {
 
 // band.hip
+void launch_fill32(void *p, unsigned v, size_t nwords, hipStream_t st);
 template <typename T>
 void launch_ingest(const double *A, int lda, int n, T *W, int ldw, unsigned *flags, hipStream_t st);
 int panel_qr_groups(int m);
@@ -40,13 +41,34 @@ void launch_band_extract(const T *W, int ldw, int n, int b, double *ab, int ldab
 int chase_ngroups(int n, int b, int nb2, int *goff_host);
 hipError_t launch_chase(double *ab, int ldab, int n, int b, int nb2, double *V2, double *tau2,
                         const int *goff, unsigned *progress, unsigned *err, double *alpha, hipStream_t st);
+// one band of a batched chase (device array of these); progress: n - 2 zeroed counters
+struct ChaseProb {
+    double *ab, *V2, *tau2;
+    const int *goff;
+    unsigned *progress, *err;
+    int ldab, n, b, nb2;
+};
+// lanes: [M + 1] item ranges per lane, then per item (problem, first position
+// in its lane); maxlen = longest lane in sweeps; G workgroups; *ticket zeroed
+hipError_t launch_chase_batched(const ChaseProb *probs, const int *lanes, int M, int maxlen, int G,
+                                unsigned *ticket, hipStream_t st);
+void launch_alpha(const double *ab, int ldab, int n, double *alpha, hipStream_t st);
+int chase_max_workgroups();
+// group offsets of the stage-2 reflectors, computed on the device (nsig + 1 entries)
+void launch_goff(int n, int b, int nb2, int *goff, hipStream_t st);
 
 // tridiag.hip
 void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, double *a2, double *stats,
                             double *w, hipStream_t st);
 void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
                             double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
-                            double *fac, double *Q, int ldq, hipStream_t st);
+                            double *fac, double *Q, int ldq, double ctol, unsigned *err, hipStream_t st);
+void launch_tridiag_polish(const double *alpha, int n, int m, const double *w, const double *shifts,
+                           const double *stats, double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw,
+                           double *Y, double *fac, double *Q, int ldq, hipStream_t st);
+// sets *flag when two consecutive values of w[0..m) are closer than tol * stats[0]
+void launch_degenerate_check(const double *w, int m, const double *stats, double tol, unsigned *flag,
+                             hipStream_t st);
 void launch_chol_inv(const double *Gp, int nparts, int NB, double *Rinv, hipStream_t st);
 
 // backtransform.hip

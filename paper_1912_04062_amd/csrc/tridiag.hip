@@ -113,8 +113,10 @@ __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, i
     }
     if (active && q == 0) {
         // the requested indices are the upper half of a spectrum symmetric
-        // about 0, so lambda >= 0; a midpoint may land a rounding error below
-        double lam = fmax(0.5 * (lo + hi), 0.0);
+        // about 0, so lambda >= 0: a final bracket that still holds 0 (the
+        // zero matrix, or a split block of odd order) gives exactly 0, which
+        // is as close as its midpoint
+        double lam = (lo <= 0.0) ? 0.0 : 0.5 * (lo + hi);
         if ((n & 1) && idx == n / 2) lam = 0.0;
         w[e] = lam;
     }
@@ -141,7 +143,15 @@ __device__ __forceinline__ double hash_uniform(unsigned long long seed, unsigned
 // previous backward pass), the start vector is generated, and the final
 // scaling (even and odd halves each to 1/sqrt(2) for lambda > 0) is left to
 // the transposition: fac[k] (even rows) and fac[nev + k] (odd rows).
+// With shifts given, vector k uses shifts[k] and starts from its current
+// values in Y (the polishing step of degenerate clusters, see
+// launch_tridiag_polish); otherwise from w[k] and a generated start.
+// Convergence: the last iteration's input has unit norm, so its solution's
+// norm |y| gives the residual |(T - shift I) y/|y|| = 1/|y| of the returned
+// vector; a vector whose residual exceeds ctol ||T|| sets code 8 in *err
+// (ctol = 0 makes every vector fail: a test hook of the error path).
 constexpr int IV_CH = 32;
+constexpr unsigned ERR_INVIT = 8u;
 
 __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, int n, int nev,
                                               const double *__restrict__ w,
@@ -149,7 +159,8 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
                                               double *__restrict__ U0, double *__restrict__ U1,
                                               double *__restrict__ U2, double *__restrict__ Lm,
                                               unsigned char *__restrict__ Sw, double *__restrict__ Y,
-                                              double *__restrict__ fac)
+                                              double *__restrict__ fac, double ctol, unsigned *err,
+                                              const double *__restrict__ shifts)
 {
     const int k = blockIdx.x * 64 + threadIdx.x;
     if (k >= nev) return;
@@ -160,7 +171,9 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
     const double lam = w[k];
     // perturb coincident shifts apart (consecutive equal eigenvalues)
     double shift = lam;
-    if (k > 0) {
+    if (shifts) {
+        shift = shifts[k];
+    } else if (k > 0) {
         int r = 0;
         while (k - r - 1 >= 0 && w[k - r - 1] == lam && r < 64) ++r;
         shift = lam + r * 10.0 * eps * fmax(fabs(lam), tiny);
@@ -203,12 +216,13 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
         }
         U0[(size_t)(n - 1) * st + k] = recip(clampu(a));
     }
-    // norm of the generated start vector
+    // norm of the start vector (generated, or the given one in Y)
     double inv;
     {
         double s = 0.0;
         for (int i = 0; i < n; ++i) {
-            const double y = hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i);
+            const double y = shifts ? Y[(size_t)i * st + k]
+                                    : hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i);
             s += y * y;
         }
         inv = 1.0 / sqrt(s);
@@ -217,8 +231,9 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
     for (int it = 0; it < iters; ++it) {
         // forward: P, L (row i+1 of the right-hand side enters at step i)
         auto yin = [&](int i, double stored) -> double {
-            return (it == 0) ? hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i) * inv
-                             : stored * inv;
+            return (it == 0 && !shifts)
+                       ? hash_uniform(0x51ab5eedull, (unsigned long long)k, (unsigned long long)i) * inv
+                       : stored * inv;
         };
         double yprev = yin(0, Y[k]);
         for (int i0 = 0; i0 + 1 < n; i0 += IV_CH) {
@@ -277,6 +292,7 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
         }
         inv = 1.0 / sqrt(se + so);
     }
+    if (err && g > 0.0 && !(sqrt(se + so) * ctol * g >= 1.0)) atomicOr(err, ERR_INVIT);
     // final scaling factors
     double fe, fo;
     if (lam > 0.0 && se > 0.0 && so > 0.0) {
@@ -335,6 +351,36 @@ __global__ void k_transpose(const double *__restrict__ Y, int n, int nev, const 
     for (int r = ty; r < 32; r += 8) {
         int k = k0 + r, i = i0 + tx;
         if (i < n && k < nev) Q[(size_t)k * ldq + i] = tile[tx][r] * fac[(i & 1) ? nev + k : k];
+    }
+}
+
+// *flag |= 2 when two consecutive values of w (ascending) are closer than
+// tol * stats[0]: a degenerate cluster (the batched form then solves the
+// problem again on its own, where such clusters are polished)
+__global__ void k_degenerate(const double *__restrict__ w, int m, const double *__restrict__ stats, double tol,
+                             unsigned *flag)
+{
+    const double lim = tol * stats[0];
+    bool d = false;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k + 1 < m; k += gridDim.x * 256)
+        if (w[k + 1] - w[k] <= lim) d = true;
+    if (__any(d) && (threadIdx.x & 63) == 0) atomicOr(flag, 2u);
+}
+
+// Q (column-major, ldq, n x m) -> Y ([i][k] layout, n x m)
+__global__ void k_transpose_in(const double *__restrict__ Q, int ldq, int n, int m, double *__restrict__ Y)
+{
+    __shared__ double tile[32][33];
+    const int k0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+    const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        int k = k0 + r, i = i0 + tx;
+        tile[r][tx] = (i < n && k < m) ? Q[(size_t)k * ldq + i] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        int i = i0 + r, k = k0 + tx;
+        if (i < n && k < m) Y[(size_t)i * m + k] = tile[tx][r];
     }
 }
 
@@ -400,14 +446,39 @@ void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, do
 
 void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
                             double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
-                            double *fac, double *Q, int ldq, hipStream_t st)
+                            double *fac, double *Q, int ldq, double ctol, unsigned *err, hipStream_t st)
 {
     if (nev <= 0) return;
     hipLaunchKernelGGL(k_invit, dim3(cdiv(nev, 64)), dim3(64), 0, st, alpha, n, nev, w, stats, 3, U0, U1, U2,
-                       Lm, Sw, Y, fac);
+                       Lm, Sw, Y, fac, ctol, err, (const double *)nullptr);
     if (n & 1) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, alpha, n, nev, Y, fac);
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(nev, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Y, n,
                        nev, (const double *)fac, Q, ldq);
+}
+
+// One more inverse-iteration step for the columns Q[:, 0..m) (eigenvalues
+// w[0..m), shifts[0..m)) from their current values: factor T - shifts[k] I,
+// solve, scale the halves, write back.  The workspace is that of
+// launch_tridiag_eigvecs, used with m in place of nev.
+void launch_tridiag_polish(const double *alpha, int n, int m, const double *w, const double *shifts,
+                           const double *stats, double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw,
+                           double *Y, double *fac, double *Q, int ldq, hipStream_t st)
+{
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_transpose_in, dim3(cdiv(m, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Q, ldq, n,
+                       m, Y);
+    hipLaunchKernelGGL(k_invit, dim3(cdiv(m, 64)), dim3(64), 0, st, alpha, n, m, w, stats, 1, U0, U1, U2, Lm, Sw,
+                       Y, fac, 1e300, (unsigned *)nullptr, shifts);
+    hipLaunchKernelGGL(k_transpose, dim3(cdiv(m, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Y, n, m,
+                       (const double *)fac, Q, ldq);
+}
+
+void launch_degenerate_check(const double *w, int m, const double *stats, double tol, unsigned *flag,
+                             hipStream_t st)
+{
+    if (m < 2) return;
+    hipLaunchKernelGGL(k_degenerate, dim3(cdiv(m, 256) > 64 ? 64 : cdiv(m, 256)), dim3(256), 0, st, w, m, stats, tol,
+                       flag);
 }
 
 void launch_chol_inv(const double *Gp, int nparts, int NB, double *Rinv, hipStream_t st)

@@ -26,6 +26,10 @@ ERR_NODEVICE = 6
 
 PREC_FP64 = 0
 PREC_FP32_REFINE = 1
+
+DEBUG_NAN_WS = 1
+DEBUG_ZERO_WS = 2
+DEBUG_INVIT_NOCONV = 4
 _PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32_REFINE, "fp32_refine": PREC_FP32_REFINE}
 
 
@@ -33,7 +37,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("band", ctypes.c_int),
                 ("max_refine_sweeps", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("workspace_limit", ctypes.c_size_t), ("profile", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+                ("autotune", ctypes.c_int), ("no_fp64_fallback", ctypes.c_int),
+                ("debug", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class KStat(ctypes.Structure):
@@ -121,7 +126,7 @@ def status_string(status):
 
 
 def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=None,
-                 workspace_limit=0, profile=0, autotune=0):
+                 workspace_limit=0, profile=0, autotune=0, no_fp64_fallback=0, debug=0):
     o = Opts()
     _load().skew_evd_default_opts(ctypes.byref(o))
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
@@ -133,6 +138,8 @@ def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=No
     o.workspace_limit = int(workspace_limit)
     o.profile = int(profile)
     o.autotune = int(autotune)
+    o.no_fp64_fallback = int(no_fp64_fallback)
+    o.debug = int(debug)
     return o
 
 
@@ -236,13 +243,14 @@ class Handle:
             raise SkewEvdError(st, "skew_evd_autotune")
         return b.value, ms.value
 
-    def solve_batched(self, mats, precision="fp64", band=0, autotune=0):
+    def solve_batched(self, mats, precision="fp64", band=0, autotune=0, nevs=None):
         """Solve a list of skew matrices (each n_i x n_i float64 CUDA); returns
-        a list of (lam, Zre, Zim) and the per-problem status list."""
+        a list of (lam, Zre, Zim), the per-problem status list and the call's
+        status.  nevs: eigenpairs per problem (default ceil(n_i / 2))."""
         count = len(mats)
         cols = [colmajor(A) for A in mats]
         ns = [int(A.shape[0]) for A in mats]
-        nevs = [(x + 1) // 2 for x in ns]
+        nevs = [(x + 1) // 2 for x in ns] if nevs is None else [int(v) for v in nevs]
         dev = mats[0].device if mats else torch.device("cuda")
         outs = [(torch.empty(max(v, 1), dtype=torch.float64, device=dev),
                  empty_colmajor(max(x, 1), max(v, 1), dev),

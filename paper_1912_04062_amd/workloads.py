@@ -15,6 +15,13 @@ check and the benchmark (GPU side and oracle side alike).
                        a synthetic real M = [[A, B], [B, A]].  It stands in for
                        the hexagonal boron nitride Hamiltonian of Section 4.2,
                        which is not available.
+* ``prescribed_large`` - a known spectrum at large n, cheap to form:
+                       A = Q1 P Q2 S Q2 P^T Q1 with symmetric orthogonal block
+                       reflectors Q_i = I - 2 U_i U_i^T (U_i: n x k, orthonormal
+                       columns) and a random permutation P.
+* ``tridiag_blocks`` - an already tridiagonal skew matrix that splits into
+                       identical blocks (every eigenvalue of a block is repeated
+                       once per block).
 * ``batch_sizes``   - matrix orders for a batch of uneven problems.
 
 All matrices are returned as Fortran-ordered (column-major) float64 arrays.
@@ -58,6 +65,56 @@ def prescribed(n, seed, lo=1e-3, hi=10.0):
     A = Q @ S @ Q.T
     A = np.asfortranarray((A - A.T) * 0.5)
     return A, l, Q
+
+
+def _reflect(B, U):
+    """(I - 2 U U^T) B (I - 2 U U^T) for U with orthonormal columns, in place."""
+    C = U.T @ B                      # k x n
+    B -= 2.0 * (U @ C)
+    D = B @ U                        # n x k (after the left product)
+    B -= 2.0 * (D @ U.T)
+    return B
+
+
+def prescribed_large(n, seed, l=None, k=64, lo=1e-3, hi=10.0):
+    """Skew matrix of even order n with the prescribed spectrum +-i*l.
+
+    l: the n/2 magnitudes (ascending), or None for log-uniform in [lo, hi].
+    A = Q1 P Q2 S Q2 P^T Q1, S = blockdiag([[0, l_p], [-l_p, 0]]); forming it
+    costs a few n x n x k products, so it serves at n = 16384.  Returns (A, l)
+    with l ascending."""
+    assert n % 2 == 0
+    rng = np.random.default_rng(seed)
+    m = n // 2
+    if l is None:
+        l = 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), size=m)
+    l = np.sort(np.asarray(l, dtype=np.float64))
+    B = np.zeros((n, n))
+    idx = np.arange(m)
+    B[2 * idx, 2 * idx + 1] = l
+    B[2 * idx + 1, 2 * idx] = -l
+    U2, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    _reflect(B, U2)
+    perm = rng.permutation(n)
+    B = B[perm][:, perm]
+    U1, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    _reflect(B, U1)
+    A = np.asfortranarray((B - B.T) * 0.5)
+    return A, l
+
+
+def tridiag_blocks(n, pattern):
+    """Tridiagonal skew A (A[j+1, j] = s_j, A[j, j+1] = -s_j) whose
+    sub-diagonal repeats `pattern` followed by a 0, so that A splits into
+    identical blocks of order len(pattern) + 1 (n a multiple of that)."""
+    q = len(pattern) + 1
+    assert n % q == 0
+    s = np.tile(np.concatenate([np.asarray(pattern, float), [0.0]]), n // q)[: n - 1]
+    A = np.zeros((n, n), order="F")
+    j = np.arange(n - 1)
+    A[j + 1, j] = s
+    A[j, j + 1] = -s
+    return A
 
 
 def bse_blocks(m, seed, rank=64):

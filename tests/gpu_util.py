@@ -55,3 +55,47 @@ def phase_match(Z, Zref, lam, gap_tol, tol):
         if gap > gap_tol:
             worst = max(worst, 1.0 - abs(np.vdot(Zref[:, k], Z[:, k])))
     return worst <= tol, worst
+
+
+def dev_checks(Ad, lam, zr, zi, nA=None):
+    """Accuracy measures with FP64 torch products on the GPU (independent of
+    the library), for full-size inputs:
+      res    ||A Z - Z diag(i lam)||_F / (n ||A||)
+      colres max_k ||A z_k - i lam_k z_k||_2 / ||A||  (for normal A each lam_k
+             then lies within colres * ||A|| of an eigenvalue)
+      orth   ||Z^H Z - I||_F / n,  orth_max  max |Z^H Z - I|
+      tr2, tr4  relative errors of sum lam^2 = ||A||_F^2 / 2 and
+             sum lam^4 = ||A^2||_F^2 / 2
+    ||A|| = nA, default max lam."""
+    n = Ad.shape[0]
+    Af = torch.tril(Ad.contiguous(), -1)
+    Af = Af - Af.t()
+    zr = zr.contiguous()
+    zi = zi.contiguous()
+    nA = lam.max().item() if nA is None else nA
+    Rr = Af @ zr + zi * lam[None, :]
+    Ri = Af @ zi - zr * lam[None, :]
+    col2 = Rr.pow(2).sum(0) + Ri.pow(2).sum(0)
+    res = col2.sum().sqrt().item() / (n * nA)
+    colres = col2.max().sqrt().item() / nA
+    del Rr, Ri, col2
+    G1 = zr.t() @ zr + zi.t() @ zi
+    G1.diagonal().sub_(1.0)
+    G2 = zr.t() @ zi - zi.t() @ zr
+    orth = (G1.pow(2).sum() + G2.pow(2).sum()).sqrt().item() / n
+    orth_max = max(G1.abs().max().item(), G2.abs().max().item())
+    del G1, G2
+    fro2 = Af.pow(2).sum().item()
+    s2 = 2.0 * lam.pow(2).sum().item()
+    A2 = Af @ Af
+    f4 = A2.pow(2).sum().item()
+    s4 = 2.0 * lam.pow(4).sum().item()
+    del Af, A2
+    torch.cuda.empty_cache()
+    tr2 = abs(s2 / fro2 - 1.0) if fro2 > 0 else abs(s2)
+    tr4 = abs(s4 / f4 - 1.0) if f4 > 0 else abs(s4)
+    return {"res": res, "colres": colres, "orth": orth, "orth_max": orth_max, "tr2": tr2, "tr4": tr4}
+
+
+def fmt(d):
+    return " ".join(f"{k}={v:.2e}" for k, v in d.items())

@@ -1,0 +1,189 @@
+"""GPU edge cases of the solver through the C-ABI.
+
+* Clusters wider than the fixed Gram-Schmidt window (1024 vectors) at
+  nev > 2048: the zero matrix, a prescribed spectrum with two eigenvalues of
+  multiplicity 2048 each, and a tridiagonal input that splits into identical
+  blocks.  Every eigenvalue is known exactly; orthogonality is asserted both
+  normalized (||Z^H Z - I||_F / n <= 1e-13) and entrywise (<= 1e-12).
+* Padded leading dimensions (lda > n, ldz > n) on input and outputs.
+* Workspace contents: a solve on a workspace filled with NaN bytes and one on
+  a zeroed workspace give bitwise equal results (no kernel reads workspace it
+  has not written), in both forms and with the second stream in use.
+* Error paths forced from the host: the inverse iteration's convergence test
+  (debug hook) reports NOCONV; the batched form refuses the precision form.
+"""
+import numpy as np
+import pytest
+
+from paper_1912_04062_amd import workloads as wl
+
+from gpu_util import TOL_EIG, TOL_ORTH, TOL_RES, dev_checks, fmt, metrics, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_1912_04062_amd import skewevd
+    return skewevd.Handle()
+
+
+def _wide(h, A, exact, label):
+    import torch
+    n = A.shape[0]
+    Ad = to_dev(A)
+    lam, zr, zi = h.solve(Ad)
+    torch.cuda.synchronize()
+    nA = max(float(np.max(exact)), 1.0)
+    err = np.max(np.abs(lam.cpu().numpy() - exact)) / nA
+    c = dev_checks(Ad, lam, zr, zi, nA=nA)
+    print(f"  {label}: eig err={err:.2e} {fmt(c)}", flush=True)
+    assert err <= TOL_EIG
+    assert c["res"] <= TOL_RES and c["colres"] <= 1e-12
+    assert c["orth"] <= TOL_ORTH and c["orth_max"] <= 1e-12
+    return lam
+
+
+def test_cluster_zero_matrix_8192(h):
+    n = 8192
+    print(f"zero matrix n={n}", flush=True)
+    lam = _wide(h, np.zeros((n, n), order="F"), np.zeros(n // 2), "zero")
+    assert bool((lam == 0).all())
+
+
+def test_cluster_repeated_eigenvalues_8192(h):
+    n = 8192
+    print(f"repeated l_k n={n}", flush=True)
+    l = np.repeat([1.0, 2.0], n // 4)           # two clusters of 2048 vectors
+    A, l = wl.prescribed_large(n, 61, l=l)
+    _wide(h, A, l, "repeated")
+
+
+def test_cluster_identical_tridiagonal_blocks_8192(h):
+    n = 8192
+    print(f"identical tridiagonal blocks n={n}", flush=True)
+    pat = [1.0, 2.0, 3.0]                        # blocks of order 4
+    A = wl.tridiag_blocks(n, pat)
+    T = np.diag(pat, 1) + np.diag(pat, -1)
+    ev = np.sort(np.linalg.eigvalsh(T))[2:]      # the two non-negative ones
+    exact = np.repeat(ev, n // 4)                # each 2048 times
+    _wide(h, A, exact, "blocks")
+
+
+@pytest.mark.parametrize("n", [333, 1200])
+def test_padded_leading_dimensions(h, n):
+    import torch
+    from paper_1912_04062_amd import skewevd
+    print(f"padded lda/ldz n={n}", flush=True)
+    A = wl.random_skew(n, 70 + n)
+    big = np.full((n + 5, n + 3), np.nan, order="F")   # padding never read
+    big[:n, :n] = A
+    Abig = to_dev(big)                                 # lda = n + 5
+    Av = Abig[:n, :n]
+    nev = (n + 1) // 2
+    lam = torch.empty(nev, dtype=torch.float64, device="cuda")
+    zr = skewevd.empty_colmajor(n + 7, nev, "cuda")
+    zi = skewevd.empty_colmajor(n + 11, nev, "cuda")
+    zr.fill_(7.0)
+    zi.fill_(-7.0)
+    l1, r1, i1 = h.solve(Av, out=(lam, zr[:n], zi[:n]))
+    torch.cuda.synchronize()
+    assert r1.stride(1) == n + 7 and i1.stride(1) == n + 11
+    l0, r0, i0 = h.solve(to_dev(A))
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l0) and torch.equal(r1, r0) and torch.equal(i1, i0)
+    assert bool((zr[n:] == 7.0).all()) and bool((zi[n:] == -7.0).all())   # rows past n untouched
+    lam_np = l1.cpu().numpy()
+    Z = r1.cpu().numpy() + 1j * i1.cpu().numpy()
+    res, orth, _ = metrics(A, lam_np, Z)
+    assert res <= TOL_RES and orth <= TOL_ORTH
+
+
+@pytest.mark.parametrize("n,precision", [(1500, "fp64"), (4100, "fp64"), (1500, "fp32"), (4100, "fp32")])
+def test_workspace_contents_do_not_matter(h, n, precision):
+    """NaN-filled versus zeroed workspace: bitwise equal outputs.  n = 4100
+    uses the second stream (T factors beside the inverse iteration)."""
+    import torch
+    from paper_1912_04062_amd import skewevd
+    print(f"workspace NaN vs zero n={n} {precision}", flush=True)
+    Ad = to_dev(wl.random_skew(n, 80 + n))
+    outs = []
+    for dbg in (skewevd.DEBUG_NAN_WS, skewevd.DEBUG_ZERO_WS, skewevd.DEBUG_NAN_WS):
+        o = skewevd.default_opts(precision, debug=dbg)
+        lam, zr, zi = h.solve(Ad, opts=o)
+        torch.cuda.synchronize()
+        outs.append((lam.clone(), zr.clone(), zi.clone(), h.last_info.refine_sweeps))
+    print(f"  sweeps {[x[3] for x in outs]}", flush=True)
+    for k in (1, 2):
+        assert outs[k][3] == outs[0][3]
+        for a, b in zip(outs[0][:3], outs[k][:3]):
+            assert torch.equal(a, b)
+    assert bool(torch.isfinite(outs[0][1]).all())
+
+
+def test_invit_noconv_reported(h):
+    from paper_1912_04062_amd import skewevd
+    A = wl.random_skew(200, 91)
+    o = skewevd.default_opts(debug=skewevd.DEBUG_INVIT_NOCONV)
+    with pytest.raises(skewevd.SkewEvdError) as e:
+        h.solve(to_dev(A), opts=o)
+    assert e.value.status == skewevd.ERR_NOCONV
+    assert "inverse iteration" in skewevd.status_string(skewevd.ERR_NOCONV)
+    lam, _, _ = h.solve(to_dev(A))                  # the handle still works
+    assert np.isfinite(lam.cpu().numpy()).all()
+
+
+def test_batched_refuses_precision_form(h):
+    mats = [to_dev(wl.random_skew(100, 1))]
+    _, _, st = h.solve_batched(mats, precision="fp32")
+    assert st == -10
+
+
+@pytest.mark.skip(reason="two benchmark runs of the batched precision form ended in a host "
+                         "segmentation fault at process exit whose cause is not shown; the "
+                         "batched form refuses the precision form (argument -10) until it is")
+def test_batched_precision_form():
+    pass
+
+
+def test_batched_mixed_problems(h):
+    """One batched call over problems of every kind: tiny orders, a partial
+    spectrum, an order above the batched path's limit (solved on its own), a
+    degenerate cluster (flagged on the device and solved again on its own), a
+    zero matrix and a non-finite input (its own status, the others unaffected).
+    Every result is bitwise equal to the single solve of the same problem."""
+    import torch
+    from paper_1912_04062_amd import skewevd
+    print("batched mixed", flush=True)
+    mats, nevs = [], []
+    for n in (1, 2, 3, 65, 300):
+        mats.append(wl.random_skew(n, 500 + n))
+        nevs.append((n + 1) // 2)
+    mats.append(wl.random_skew(301, 77))
+    nevs.append(40)                                   # partial spectrum
+    mats.append(wl.tridiag_blocks(1024, [1.0, 2.0, 3.0]))
+    nevs.append(512)                                  # two clusters of 256
+    mats.append(np.zeros((200, 200), order="F"))
+    nevs.append(100)
+    bad = wl.random_skew(128, 3)
+    bad[70, 5] = np.inf
+    mats.append(bad)
+    nevs.append(64)
+    mats.append(wl.random_skew(4100, 8))              # above the batched path's limit
+    nevs.append(2050)
+    dev = [to_dev(A) for A in mats]
+    res, status, st = h.solve_batched(dev, nevs=nevs)
+    torch.cuda.synchronize()
+    print(f"  status {status} -> {st}", flush=True)
+    assert st == skewevd.ERR_NONFINITE
+    for k, (A, Ad, nv, (lam, zr, zi), s) in enumerate(zip(mats, dev, nevs, res, status)):
+        if k == 8:
+            assert s == skewevd.ERR_NONFINITE
+            continue
+        assert s == 0, (k, s)
+        l1, r1, i1 = h.solve(Ad, nev=nv)
+        torch.cuda.synchronize()
+        assert torch.equal(lam, l1) and torch.equal(zr, r1) and torch.equal(zi, i1), k
+        if A.shape[0] > 1:
+            c = dev_checks(Ad, lam, zr, zi, nA=max(lam.max().item(), 1.0))
+            assert c["colres"] <= 1e-12 and c["orth_max"] <= 1e-12, (k, c)
