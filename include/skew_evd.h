@@ -175,6 +175,30 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n,
                      double *const *Z_im, const skew_evd_opts *opts,
                      skew_evd_info *info, int *status);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The FP64 solver of skew_evd_ex with default options for orders
+ * n <= SKEW_EVD_NOALLOC_NMAX, on the HIP stream `hip_stream` (a hipStream_t,
+ * NULL = the null stream) of the current device; arguments as for skew_evd_ex
+ * (device pointers; only the strict lower triangle of A is read).  It calls no
+ * hipMalloc, hipFree, hipHostMalloc or event/stream creation: its workspace is
+ * a fixed device array of SKEW_EVD_NOALLOC_BYTES bytes that the library holds
+ * on every device it runs on until the process ends, and its host-side state
+ * is fixed storage, one slot per device.  Every call on a device shares that
+ * device's array, which keeps the last call's contents (every call clears what
+ * it needs cleared), so calls that overlap on one device -- from several host
+ * threads or streams -- race and must be serialized by the caller.
+ * Synchronous with respect to hip_stream: it returns after the results are in
+ * lambda / Z_re / Z_im (it reads status words back, so it cannot itself be
+ * captured in a graph).
+ * Errors: -1 n, -2 A, -3 lda, -4 nev, -5 lambda, -6 Z_re, -7 ldzr, -8 Z_im,
+ * -9 ldzi; SKEW_EVD_ERR_NOMEM (before any device work) when
+ * n > SKEW_EVD_NOALLOC_NMAX; otherwise the statuses of skew_evd_ex. */
+#define SKEW_EVD_NOALLOC_NMAX 512
+#define SKEW_EVD_NOALLOC_BYTES (48u << 20)
+int skew_evd_noalloc(int n, const double *A, int lda, int nev, double *lambda,
+                     double *Z_re, int ldzr, double *Z_im, int ldzi, void *hip_stream);
+
 /* Stage entry points (building blocks, also used by the stage-level tests). */
 
 /* Full-to-band reduction (Section 2.3.2): B = Q_band^T A Q_band with semi-

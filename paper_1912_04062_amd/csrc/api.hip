@@ -61,6 +61,7 @@ struct skew_evd_handle_s {
     size_t kopen[SKEW_EVD_NKERN] = {};
     int refine_passes = 0;
     bool async = false;             // enqueue only: no stage events, no host waits (batched form)
+    bool noalloc = false;           // allocation-free entry point: fixed buffers, no events created
     double *lam_host = nullptr;     // pinned: eigenvalues, ||T||, then the polishing shifts
     size_t lam_cap = 0;
     int polish_lo = 0, polish_hi = 0;   // vectors [lo, hi) get the polishing step
@@ -90,10 +91,16 @@ struct Layout {
     size_t W, Vall, Tall, tauall, Ypart, Y0, Wd, Gp, Tx, part, ab, goff, V2, tau2, T2, V2t, alpha, a2, stats,
         lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, pshift, Qd, Z, cq, cqGp, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
         rstat, Tm, total;
-    std::vector<size_t> Voff;
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// offset (elements) of panel j's V_j in Vall: sum over i < j of (n - (i+1) b) b
+size_t voff(const Plan &p, int j)
+{
+    const size_t n = p.n, b = p.b, jj = j;
+    return b * (jj * n - b * jj * (jj + 1) / 2);
+}
 
 int tn_parts_max() { return 32; }
 
@@ -118,13 +125,8 @@ Layout plan_layout(const Plan &p)
         return o;
     };
     L.W = take(es * n * n);
-    L.Voff.clear();
     size_t vtot = 0;
-    for (int j = 0; j < p.npanels; ++j) {
-        L.Voff.push_back(vtot);
-        size_t m = n - (size_t)(j + 1) * b;
-        vtot += m * b;
-    }
+    for (int j = 0; j < p.npanels; ++j) vtot += (n - (size_t)(j + 1) * b) * b;
     L.Vall = take(es * vtot);
     L.Tall = take(sizeof(double) * (size_t)std::max(p.npanels, 1) * b * b);
     L.Tm = take(sizeof(double) * (size_t)(p.npanels / 2 + 1) * 4 * b * b);
@@ -347,7 +349,7 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
     unsigned bar_base = 0;
     for (int j = 0; j < p.npanels; ++j) {
         const int c0 = j * b, r0 = c0 + b, m = n - r0;
-        T *Vd = ptr<T>(h, L.Vall) + L.Voff[j];
+        T *Vd = ptr<T>(h, L.Vall) + voff(p, j);
         double *Tf = ptr<double>(h, L.Tall) + (size_t)j * b * b;
         double *tauj = ptr<double>(h, L.tauall) + (size_t)j * b;
         HCHK(kt_begin(h, SKEW_EVD_K_PANEL));
@@ -455,8 +457,12 @@ int fetch_windows(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
 {
     (void)p;
     if (h->async) return SKEW_EVD_OK;
-    if (!h->win_ev) HCHK(hipEventCreateWithFlags(&h->win_ev, hipEventDisableTiming));
+    if (!h->win_ev && !h->noalloc) HCHK(hipEventCreateWithFlags(&h->win_ev, hipEventDisableTiming));
     if ((size_t)2 * nev + 1 > h->lam_cap) {
+        if (h->noalloc) {
+            snprintf(g_errtext, sizeof(g_errtext), "eigenvalue buffer of the allocation-free path too small");
+            return SKEW_EVD_ERR_NOMEM;
+        }
         if (h->lam_host) HCHK(hipHostFree(h->lam_host));
         h->lam_host = nullptr;
         h->lam_cap = 0;
@@ -466,7 +472,7 @@ int fetch_windows(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
     HCHK(hipMemcpyAsync(h->lam_host, lam_dev, sizeof(double) * nev, hipMemcpyDeviceToHost, h->stream));
     HCHK(hipMemcpyAsync(h->lam_host + nev, ptr<double>(h, L.stats), sizeof(double), hipMemcpyDeviceToHost,
                         h->stream));
-    HCHK(hipEventRecord(h->win_ev, h->stream));
+    if (h->win_ev) HCHK(hipEventRecord(h->win_ev, h->stream));
     return SKEW_EVD_OK;
 }
 
@@ -477,7 +483,8 @@ int plan_windows(skew_evd_handle h, const Plan &p, int nev)
     h->win0.clear();
     h->polish_lo = h->polish_hi = 0;
     if (h->async) return SKEW_EVD_OK;       // fixed windows; degenerate clusters are flagged on the device
-    HCHK(hipEventSynchronize(h->win_ev));
+    if (h->win_ev) HCHK(hipEventSynchronize(h->win_ev));
+    else HCHK(hipStreamSynchronize(h->stream));
     const double *lam = h->lam_host;
     const double g = h->lam_host[nev];      // ||T||_inf
     if (!windows_fixed(p, nev)) {
@@ -626,8 +633,8 @@ void launch_bt1_merges(skew_evd_handle h, const Plan &p, const Layout &L, double
     int q = 0;
     for (int j0 = P - 2; j0 >= 0; j0 -= 2, ++q) {
         const int m0 = n - (j0 + 1) * b, m1 = m0 - b;
-        const T *V0 = ptr<T>(h, L.Vall) + L.Voff[j0];
-        const T *V1 = ptr<T>(h, L.Vall) + L.Voff[j0 + 1];
+        const T *V0 = ptr<T>(h, L.Vall) + voff(p, j0);
+        const T *V1 = ptr<T>(h, L.Vall) + voff(p, j0 + 1);
         int S = skew::launch_gemm_tn_part<T>(V0 + b, m0, V1, m1, b, b, m1, Gp, st);
         skew::launch_merge_t(ptr<double>(h, L.Tall) + (size_t)j0 * b * b,
                              ptr<double>(h, L.Tall) + (size_t)(j0 + 1) * b * b, Gp, S, b,
@@ -704,8 +711,8 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L, bool 
         int q = 0;
         for (int j0 = P - 2; j0 >= 0; j0 -= 2, ++q) {
             const int m0 = n - (j0 + 1) * b, m1 = m0 - b;
-            const T *V0 = ptr<T>(h, L.Vall) + L.Voff[j0];
-            const T *V1 = ptr<T>(h, L.Vall) + L.Voff[j0 + 1];
+            const T *V0 = ptr<T>(h, L.Vall) + voff(p, j0);
+            const T *V1 = ptr<T>(h, L.Vall) + voff(p, j0 + 1);
             skew::launch_bt1_block<T>(Z, n, (j0 + 1) * b, m0, 2 * nev, V0, b, V1, m1,
                                       ptr<double>(h, L.Tm) + (size_t)q * 4 * b * b, 2 * b, ptr<double>(h, L.Wp),
                                       ptr<T>(h, L.Wt2), st);
@@ -713,7 +720,7 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L, bool 
         }
         if (P % 2 == 1) {                    // panel 0 alone
             const int m0 = n - b;
-            const T *V0 = ptr<T>(h, L.Vall) + L.Voff[0];
+            const T *V0 = ptr<T>(h, L.Vall) + voff(p, 0);
             const double *Tf = ptr<double>(h, L.Tall);
             skew::launch_bt1_block<T>(Z, n, b, m0, 2 * nev, V0, b, nullptr, 0, Tf, b, ptr<double>(h, L.Wp),
                                       ptr<T>(h, L.Wt2), st);
@@ -725,7 +732,7 @@ int stage_backtransform(skew_evd_handle h, const Plan &p, const Layout &L, bool 
     }
     for (int j = p.npanels - 1; j >= 0; --j) {
         const int r0 = (j + 1) * b, m = n - r0;
-        const T *Vd = ptr<T>(h, L.Vall) + L.Voff[j];
+        const T *Vd = ptr<T>(h, L.Vall) + voff(p, j);
         const double *Tf = ptr<double>(h, L.Tall) + (size_t)j * b * b;
         HCHK(kt_begin(h, SKEW_EVD_K_BT1));
         int S = skew::launch_gemm_tn_part<T>(Vd, m, Z + r0, n, b, 2 * nev, m, ptr<double>(h, L.Wp), st);
@@ -1524,6 +1531,81 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
         info->band = together.empty() ? 0 : make_plan(n[together[0]], nev[together[0]], popt[together[0]].band, 0).b;
     }
     return first;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry point.  Its workspace is the file-scope device array
+// `scratch`; each device that runs it holds its own copy from the first call
+// until the process ends.  The array's device address on a device is taken
+// once, with that device current, through hipGetSymbolAddress and kept per
+// device: host code never passes the array's name itself (a host-side stand-in,
+// not a device address).  The host-side state of a call (control words and
+// eigenvalues read back, the stage drivers' bookkeeping) is also fixed
+// storage, one slot per device, so calls on one device must not overlap.
+static __device__ __align__(256) char scratch[SKEW_EVD_NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAXDEV = 64;
+struct NoallocSlot {
+    char *ws = nullptr;                  // device address of `scratch` on this device
+    skew_evd_handle_s h;
+    unsigned ctl[64];
+    double lam[2 * SKEW_EVD_NOALLOC_NMAX + 1];
+};
+NoallocSlot g_noalloc[NOALLOC_MAXDEV];
+}  // namespace
+
+int skew_evd_noalloc(int n, const double *A, int lda, int nev, double *lambda, double *Z_re, int ldzr, double *Z_im,
+                     int ldzi, void *hip_stream)
+{
+    if (n < 0) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < std::max(1, n)) return -3;
+    if (nev < 0 || nev > (n + 1) / 2) return -4;
+    if (nev > 0 && !lambda) return -5;
+    if (nev > 0 && !Z_re) return -6;
+    if (ldzr < std::max(1, n)) return -7;
+    if (nev > 0 && !Z_im) return -8;
+    if (ldzi < std::max(1, n)) return -9;
+    if (n > SKEW_EVD_NOALLOC_NMAX) {
+        snprintf(g_errtext, sizeof(g_errtext), "n = %d exceeds the allocation-free limit n <= %d", n,
+                 SKEW_EVD_NOALLOC_NMAX);
+        return SKEW_EVD_ERR_NOMEM;
+    }
+    if (n == 0 || nev == 0) return SKEW_EVD_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAXDEV) {
+        (void)hipGetLastError();
+        snprintf(g_errtext, sizeof(g_errtext), "no usable HIP device");
+        return SKEW_EVD_ERR_NODEVICE;
+    }
+    NoallocSlot &sl = g_noalloc[dev];
+    if (!sl.ws) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_hip_error(e, "hipGetSymbolAddress(scratch)");
+            return SKEW_EVD_ERR_HIP;
+        }
+        sl.ws = (char *)p;
+        sl.h.device = dev;
+        sl.h.noalloc = true;
+        sl.h.ctl_host = sl.ctl;
+        sl.h.lam_host = sl.lam;
+        sl.h.lam_cap = 2 * SKEW_EVD_NOALLOC_NMAX + 1;
+    }
+    sl.h.ws = sl.ws;
+    sl.h.ws_bytes = SKEW_EVD_NOALLOC_BYTES;
+    sl.h.stream = (hipStream_t)hip_stream;
+    skew_evd_opts o;
+    skew_evd_default_opts(&o);
+    o.workspace_limit = SKEW_EVD_NOALLOC_BYTES;
+    const Plan p = make_plan(n, nev, 0, SKEW_EVD_PREC_FP64);
+    if (plan_layout(p).total > SKEW_EVD_NOALLOC_BYTES) {
+        snprintf(g_errtext, sizeof(g_errtext), "workspace of n = %d exceeds the allocation-free array", n);
+        return SKEW_EVD_ERR_NOMEM;
+    }
+    return solve(&sl.h, n, A, lda, nev, lambda, Z_re, ldzr, Z_im, ldzi, &o, nullptr);
 }
 
 int skew_evd_band_reduce(skew_evd_handle h, int n, const double *A, int lda, int b, double *band, int ldband)

@@ -113,6 +113,8 @@ def _load():
     lib.skew_evd_autotune.restype = ip
     lib.skew_evd_version.argtypes = []
     lib.skew_evd_version.restype = ip
+    lib.skew_evd_noalloc.argtypes = [ip, vp, ip, ip, vp, vp, ip, vp, ip, vp]
+    lib.skew_evd_noalloc.restype = ip
     _lib = lib
     return lib
 
@@ -307,6 +309,32 @@ class Handle:
         if st != OK:
             raise SkewEvdError(st, "skew_evd_tridiag_eig")
         return lam[:nev], Q[:, :nev]
+
+
+def noalloc_max_n():
+    """SKEW_EVD_NOALLOC_NMAX of the header."""
+    import re
+    hdr = os.path.join(os.path.dirname(_HERE), "include", "skew_evd.h")
+    return int(re.search(r"#define SKEW_EVD_NOALLOC_NMAX (\d+)", open(hdr).read()).group(1))
+
+
+def solve_noalloc(A, nev=None, out=None, stream=None):
+    """skew_evd_noalloc (the allocation-free entry point): A a float64 CUDA
+    tensor of order n <= noalloc_max_n(); returns (status, lam, Zre, Zim).
+    With out=(lam, Zre, Zim) (column-major) nothing is allocated here either."""
+    n = A.shape[0]
+    nev = (n + 1) // 2 if nev is None else int(nev)
+    Ac, lda = colmajor(A)
+    if out is None:
+        dev = A.device
+        out = (torch.empty(max(nev, 1), dtype=torch.float64, device=dev),
+               empty_colmajor(max(n, 1), max(nev, 1), dev), empty_colmajor(max(n, 1), max(nev, 1), dev))
+    lam, zr, zi = out
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    st = _load().skew_evd_noalloc(n, ctypes.c_void_p(Ac.data_ptr()), lda, nev, ctypes.c_void_p(lam.data_ptr()),
+                                  ctypes.c_void_p(zr.data_ptr()), zr.stride(1), ctypes.c_void_p(zi.data_ptr()),
+                                  zi.stride(1), ctypes.c_void_p(stream.cuda_stream))
+    return st, lam[:nev], zr[:n, :nev], zi[:n, :nev]
 
 
 _handles = {}

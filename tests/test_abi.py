@@ -106,3 +106,28 @@ def test_ctypes_structs_match_the_header(tmp_path):
         want.append(ctypes.sizeof(cls))
         want += [getattr(cls, f).offset for f in names]
     assert got == want
+
+
+def test_noalloc_argument_validation_without_device(lib):
+    """The allocation-free entry point checks its arguments, and refuses orders
+    above its fixed array's limit, before any device call."""
+    vp, ip = ctypes.c_void_p, ctypes.c_int
+    f = lib.skew_evd_noalloc
+    f.argtypes = [ip, vp, ip, ip, vp, vp, ip, vp, ip, vp]
+    f.restype = ip
+    nmax = int(re.search(r"#define SKEW_EVD_NOALLOC_NMAX (\d+)", open(HEADER).read()).group(1))
+    assert nmax >= 512
+    assert f(-1, None, 1, 0, None, None, 1, None, 1, None) == -1
+    assert f(4, None, 4, 1, None, None, 4, None, 4, None) == -2
+    assert f(4, vp(8), 3, 1, None, None, 4, None, 4, None) == -3
+    assert f(4, vp(8), 4, 3, None, None, 4, None, 4, None) == -4
+    assert f(4, vp(8), 4, 2, None, None, 4, None, 4, None) == -5
+    assert f(4, vp(8), 4, 2, vp(8), None, 4, None, 4, None) == -6
+    assert f(4, vp(8), 4, 2, vp(8), vp(8), 3, None, 4, None) == -7
+    assert f(4, vp(8), 4, 2, vp(8), vp(8), 4, None, 4, None) == -8
+    assert f(4, vp(8), 4, 2, vp(8), vp(8), 4, vp(8), 3, None) == -9
+    assert f(0, None, 1, 0, None, None, 1, None, 1, None) == 0
+    n = nmax + 1
+    assert f(n, vp(8), n, 1, vp(8), vp(8), n, vp(8), n, None) == 4       # NOMEM, no device touched
+    lib.skew_evd_status_string.restype = ctypes.c_char_p
+    assert b"allocation-free" in lib.skew_evd_status_string(4)
