@@ -148,5 +148,38 @@ def tridiag_eigvecs(alpha, w, seed=0x5EED):
     return Q[:, :w.size].copy()
 
 
+def bse_evd(A, B, nev=None):
+    """The Bethe-Salpeter route of Section 3 (the four BSEPACK steps), as plain
+    numpy steps around the skew-symmetric oracle above.
+
+    A (m x m, Hermitian) and B (m x m, complex symmetric) define
+    H_BS = [[A, B], [-conj(B), -conj(A)]] (Eq. BSmatrix), assumed definite
+    ([[A, B], [conj(B), conj(A)]] > 0).  Steps:
+      1. M = [[Re(A+B), Im(A-B)], [-Im(A+B), Re(A-B)]] (Eq. SymmetricM, M = JH);
+      2. Cholesky M = L L^T;
+      3. eigenpairs K z = i lambda z of the skew-symmetric K = L^T J L,
+         J = [[0, I], [-I, 0]] (the skew oracle);
+      4. back-transformation (Theorem 2 and the Cholesky factor): with
+         H = J^T M, H L^{-T} z = -i lambda L^{-T} z, so x = Q L^{-T} z,
+         Q = [[I, -iI], [I, iI]] / sqrt(2), satisfies H_BS x = lambda x.
+    x is scaled to the BSE normalization x^H S x = 1, S = diag(I, -I)
+    (unscaled, x^H S x = 1 / lambda for ||z|| = 1).
+    Returns (lam, X): the nev smallest positive eigenvalues of H_BS ascending
+    and X (2m x nev complex)."""
+    A = np.asarray(A, dtype=np.complex128)
+    B = np.asarray(B, dtype=np.complex128)
+    m = A.shape[0]
+    n = 2 * m
+    nev = m if nev is None else int(nev)
+    M = np.block([[(A + B).real, (A - B).imag], [-(A + B).imag, (A - B).real]])
+    L = np.linalg.cholesky(M)
+    J = np.block([[np.zeros((m, m)), np.eye(m)], [-np.eye(m), np.zeros((m, m))]])
+    K = L.T @ J @ L
+    lam, Z = skew_evd(np.asfortranarray(K), nev)
+    W = np.linalg.solve(L.T, Z)                       # L^{-T} z (a triangular solve)
+    X = np.vstack([W[:m] - 1j * W[m:], W[:m] + 1j * W[m:]]) / np.sqrt(2.0)
+    return lam, X * np.sqrt(lam)[None, :]
+
+
 def num_threads():
     return _load().oracle_num_threads()

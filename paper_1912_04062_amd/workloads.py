@@ -22,6 +22,8 @@ check and the benchmark (GPU side and oracle side alike).
 * ``tridiag_blocks`` - an already tridiagonal skew matrix that splits into
                        identical blocks (every eigenvalue of a block is repeated
                        once per block).
+* ``bse_complex``   - complex Hermitian A and complex symmetric B of a definite
+                       Bethe-Salpeter Hamiltonian [[A, B], [-conj(B), -conj(A)]].
 * ``batch_sizes``   - matrix orders for a batch of uneven problems.
 
 All matrices are returned as Fortran-ordered (column-major) float64 arrays.
@@ -142,6 +144,23 @@ def bse_shaped(m, seed, rank=64):
     K = L.T @ JL
     K = np.asfortranarray((K - K.T) * 0.5)
     return K, Ab, Bb
+
+
+def bse_complex(m, seed, rank=64):
+    """Complex Bethe-Salpeter blocks: A Hermitian, B complex symmetric, with
+    [[A, B], [conj(B), conj(A)]] > 0 (the definite case of Section 3).
+    A = diag(d) + V V^H / m (d ~ U[1, 10], V m x rank complex Gaussian),
+    B = 0.1 W W^T / m (W m x rank complex Gaussian): ||B|| is small against
+    A >= 1, so the block matrix is positive definite.  Returns (A, B)."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(1.0, 10.0, size=m)
+    V = (rng.standard_normal((m, rank)) + 1j * rng.standard_normal((m, rank))) / np.sqrt(2.0)
+    W = (rng.standard_normal((m, rank)) + 1j * rng.standard_normal((m, rank))) / np.sqrt(2.0)
+    A = np.diag(d).astype(np.complex128) + V @ V.conj().T / m
+    A = (A + A.conj().T) * 0.5
+    B = 0.1 * (W @ W.T) / m
+    B = (B + B.T) * 0.5
+    return np.asfortranarray(A), np.asfortranarray(B)
 
 
 def batch_sizes(count, seed, lo=64, hi=1024):

@@ -187,6 +187,54 @@ def test_bse_eigenvalues(oracle_mod, m):
 
 
 # ---------------------------------------------------------------------------
+# The Bethe-Salpeter route (Section 3, the four BSEPACK steps) around the oracle.
+def _hbs(A, B):
+    return np.block([[A, B], [-B.conj(), -A.conj()]])
+
+
+@pytest.mark.parametrize("m,seed", [(6, 1), (17, 2), (40, 3)])
+def test_bse_route_brute_force(oracle_mod, m, seed):
+    """Against a brute-force eigensolve of the non-Hermitian H_BS (numpy's
+    general eigvals): the definite H_BS has real eigenvalues +-lambda, and the
+    route returns the positive ones; H_BS x = lambda x; x^H S x = 1."""
+    A, B = wl.bse_complex(m, seed, rank=4)
+    H = _hbs(A, B)
+    ev = np.linalg.eigvals(H)
+    nH = np.abs(ev).max()
+    assert np.max(np.abs(ev.imag)) <= 1e-12 * nH           # definite: real spectrum
+    pos = np.sort(ev.real)[m:]
+    assert np.all(pos > 0)
+    lam, X = oracle_mod.bse_evd(A, B)
+    assert np.max(np.abs(lam - pos)) <= 1e-12 * nH
+    R = H @ X - X * lam[None, :]
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-12 * nH * np.max(np.linalg.norm(X, axis=0))
+    S = np.concatenate([np.ones(m), -np.ones(m)])
+    norms = np.einsum("ik,i,ik->k", X.conj(), S, X).real
+    assert np.max(np.abs(norms - 1.0)) <= 1e-12
+    # the pair of -lambda: [conj(v); conj(u)] for x = [u; v]
+    Xm = np.vstack([X[m:].conj(), X[:m].conj()])
+    assert np.max(np.linalg.norm(H @ Xm + Xm * lam[None, :], axis=0)) <= 1e-12 * nH * np.max(np.linalg.norm(X, axis=0))
+
+
+def test_bse_route_partial(oracle_mod):
+    A, B = wl.bse_complex(30, 5, rank=4)
+    lam, X = oracle_mod.bse_evd(A, B)
+    l7, X7 = oracle_mod.bse_evd(A, B, nev=7)
+    assert np.allclose(l7, lam[:7], rtol=0, atol=1e-13 * lam.max())
+    assert X7.shape == (60, 7)
+
+
+def test_bse_route_real_blocks(oracle_mod):
+    """Real A, B: M = blockdiag(A+B, A-B) and lambda^2 = eig((A+B)(A-B)),
+    an identity independent of the route's steps."""
+    m = 25
+    Ab, Bb = wl.bse_blocks(m, 8, rank=6)
+    lam, _ = oracle_mod.bse_evd(Ab.astype(complex), Bb.astype(complex))
+    ref = np.sqrt(np.sort(np.linalg.eigvals((Ab + Bb) @ (Ab - Bb)).real))
+    assert np.max(np.abs(lam - ref)) <= 1e-12 * ref.max()
+
+
+# ---------------------------------------------------------------------------
 # Invariants.
 @pytest.mark.parametrize("n", [10, 63, 128])
 def test_invariants(oracle_mod, n):
