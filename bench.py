@@ -110,8 +110,9 @@ def batch_bench(args):
     del mats
     F = sum(useful_flops(x, (x + 1) // 2) for x in sizes)
     results = {}
+    tunes = {"0": (0,), "1": (1,), "both": (0, 1)}[args.autotune]
     for form in ["fp64"]:
-        for tune in (0, 1):
+        for tune in tunes:
             h = skewevd.Handle()
             try:
                 for _ in range(max(args.warmup, 1)):
@@ -166,19 +167,109 @@ def batch_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def start_study(args):
+    """--workload start: how far the FP32 pipeline's eigenpairs are from the FP64
+    ones before any refinement, next to the gaps of the spectrum.  The FP32 form
+    runs with no refinement sweep and no FP64 fallback (WARN_REFINE, the
+    unrefined vectors); r0 is its first measured error (largest |I - X^T X|
+    entry or off-diagonal |X^T A X| / lambda_max).  A Newton step of the
+    refinement is only valid for pairs whose correction r / (relative gap) stays
+    well below 1 (the solver refuses corrections above 0.25); the line reports
+    how many adjacent pairs that excludes for r0 and for r0 scaled to BF16's
+    unit roundoff (2^-8 against FP32's 2^-24, the same pipeline in BF16)."""
+    import torch
+    from paper_1912_04062_amd import skewevd, workloads
+    n = args.n
+    A = workloads.random_skew(n, 4)
+    Ad = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+    del A
+    h = skewevd.Handle()
+    o = skewevd.default_opts("fp32", max_refine_sweeps=0, no_fp64_fallback=1)
+    lam, zr, zi = h.solve(Ad, opts=o)
+    torch.cuda.synchronize()
+    r0 = h.last_info.refine_residual
+    acc = accuracy(Ad, lam, zr, zi)
+    lam64, _, _ = h.solve(Ad)
+    torch.cuda.synchronize()
+    l = lam64.cpu().numpy()
+    lmax = float(l.max())
+    gap = np.diff(np.concatenate([[-l[0]], l]))   # the pair's distance to its neighbour (and to -lambda_0)
+    rel = gap / lmax
+    out = {"metric": "precision-form start error vs spectral gaps", "n": n, "nev": int(l.size),
+           "fp32_unrefined": {"r0": r0, "residual": acc["residual"], "orthogonality": acc["orthogonality"],
+                              "max_eig_err_rel": float(np.max(np.abs(lam.cpu().numpy() - l)) / lmax)},
+           "rel_gap": {"min": float(rel.min()), "median": float(np.median(rel)),
+                       "p01": float(np.quantile(rel, 0.01))}}
+    for name, r in (("fp32", r0), ("bf16_projected", r0 * 2.0 ** 16)):
+        out[name] = {"r0": r, "pairs_with_correction_above_0.25": int(np.sum(r / rel > 0.25)),
+                     "fraction": float(np.mean(r / rel > 0.25))}
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+def bse_bench(args):
+    """--workload bse: the Bethe-Salpeter route (skew_evd_bse: M, Cholesky,
+    K = L^T J L, the skew-symmetric solve, back-transformation) on synthetic
+    complex blocks of order m = n/2 (n = 10000 by default through --n), all m
+    positive eigenpairs.  Flops counted: (1/3) n^3 Cholesky + n^3 for the lower
+    half of K + the skew solve's F(n) + 2 n^2 (2 nev) for the triangular solve."""
+    import torch
+    from paper_1912_04062_amd import skewevd, workloads
+    n = args.n if args.n != 16384 else 10000
+    m = n // 2
+    A, B = workloads.bse_complex(m, 3)
+    Ad = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+    Bd = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().t()
+    h = skewevd.Handle()
+    nev = m
+    F = n ** 3 / 3.0 + n ** 3 + useful_flops(n, nev) + 4.0 * n * n * nev
+    for _ in range(max(args.warmup, 1)):
+        h.bse(Ad, Bd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lam, X = h.bse(Ad, Bd)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    # the skew-symmetric part alone, on a matrix of the same order
+    K = workloads.random_skew(n, 3)
+    Kd = torch.from_numpy(np.ascontiguousarray(K.T)).cuda().t()
+    h.solve(Kd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.solve(Kd)
+    torch.cuda.synchronize()
+    wskew = (time.perf_counter() - t0) / args.steps
+    h.close()
+    print(json.dumps({"metric": "Bethe-Salpeter route time-to-solution, all positive eigenpairs, TFLOP/s",
+                      "value": F / wall / 1e12, "unit": "TFLOP/s", "ms_per_step": wall * 1e3,
+                      "steps": args.steps, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"complex BSE blocks A = diag(d) + V V^H / m, B = 0.1 W W^T / m, "
+                                             f"m = {m} (order {n}), seed 3, nev = m", "n": n, "m": m,
+                                 "flops": F},
+                      "skew_solve_ms_same_order": wskew * 1e3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="dense", choices=["dense", "batch"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "batch", "start", "bse"],
                     help="dense: one matrix of order --n (the headline line); batch: 512 "
                          "uneven matrices through the batched entry point")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--nev", type=int, default=0,
+                    help="eigenpairs (0 = n/2, the headline); fewer for a partial-spectrum line")
+    ap.add_argument("--all-pairs", action="store_true",
+                    help="all n eigenpairs of both signs (the 100 %% case; the other half is a copy)")
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32", "both"])
     ap.add_argument("--check", type=int, default=1, help="untimed accuracy check of each form")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3072)
+    ap.add_argument("--autotune", default="both", choices=["0", "1", "both"],
+                    help="--workload batch: time the fixed band rule, the autotuned bands, or both")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB copied by one plain device copy before the solves (a known-size "
                          "reference for hardware byte counters); 0 = none")
@@ -189,14 +280,25 @@ def main():
         sys.exit(2)
 
     if args.workload == "batch":
+        # the batched form runs its problems on 16 streams: let the HIP runtime
+        # give each its own hardware queue (read when the runtime starts, so
+        # before torch initializes the device)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
         batch_bench(args)
+        return
+    if args.workload == "start":
+        start_study(args)
+        return
+    if args.workload == "bse":
+        bse_bench(args)
         return
 
     import torch
     from paper_1912_04062_amd import skewevd, workloads
 
     n = args.n
-    nev = (n + 1) // 2
+    nev = args.nev if args.nev > 0 else (n + 1) // 2
+    nout = n if args.all_pairs else nev
     A = workloads.random_skew(n, 4)
     Ad = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
     del A
@@ -208,9 +310,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     h = skewevd.Handle()
-    out = (torch.empty(nev, dtype=torch.float64, device="cuda"),
-           skewevd.empty_colmajor(n, nev, "cuda"), skewevd.empty_colmajor(n, nev, "cuda"))
-    F = useful_flops(n, nev)
+    out = (torch.empty(nout, dtype=torch.float64, device="cuda"),
+           skewevd.empty_colmajor(n, nout, "cuda"), skewevd.empty_colmajor(n, nout, "cuda"))
+    F = useful_flops(n, (n + 1) // 2 if args.all_pairs else nev)
     forms = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
     results = {}
     warm = max(args.warmup, 1)      # at least one untimed run (it also names the dominant kernel)
@@ -220,8 +322,10 @@ def main():
         # that kernel when it is the stage-2 application (one launch), so that
         # the timers of the many small launches stay out of the timed region
         full = None
+        def opts(prof):
+            return skewevd.default_opts(form, profile=prof, all_pairs=int(args.all_pairs))
         for w in range(warm):
-            h.solve(Ad, precision=form, out=out, profile=1)
+            h.solve(Ad, nev=nev, out=out, opts=opts(1))
             full = h.last_info.as_dict()
         torch.cuda.synchronize()
         kfull = {k: v["ms"] for k, v in full["kernels"].items()}
@@ -229,7 +333,7 @@ def main():
         infos = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            h.solve(Ad, precision=form, out=out, profile=prof)
+            h.solve(Ad, nev=nev, out=out, opts=opts(prof))
             infos.append(h.last_info.as_dict())
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
@@ -279,9 +383,10 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": f"dense random skew-symmetric A=(B-B^T)/2, B iid N(0,1), seed 4, "
-                               f"n={n}, nev={nev}; reported form: {best}",
-                   "n": n, "nev": nev, "precision": best, "band": infos[0]["band"],
-                   "useful_flops": F},
+                               f"n={n}, nev={nev}{' (all n pairs)' if args.all_pairs else ''}; "
+                               f"reported form: {best}",
+                   "n": n, "nev": nev, "all_pairs": bool(args.all_pairs), "precision": best,
+                   "band": infos[0]["band"], "useful_flops": F},
         "forms": form_summary,
         "stages_ms": stage_avg,
         "roofline": roof,

@@ -51,6 +51,8 @@ extern "C" {
 #define SKEW_EVD_ERR_NOMEM 4       /* workspace allocation failed or exceeds opts.workspace_limit */
 #define SKEW_EVD_ERR_HIP 5         /* HIP runtime error; text from skew_evd_status_string */
 #define SKEW_EVD_ERR_NODEVICE 6    /* no usable gfx950 device */
+#define SKEW_EVD_ERR_NOTDEF 7      /* skew_evd_bse: [[A, B], [conj(B), conj(A)]] is not positive
+                                      definite (the Cholesky factorization of M failed) */
 
 #define SKEW_EVD_PREC_FP64 0        /* every stage in FP64 */
 #define SKEW_EVD_PREC_FP32_REFINE 1 /* band reduction and back-transformation in FP32
@@ -75,8 +77,20 @@ typedef struct skew_evd_opts {
                                not reach refine_tol is solved again in FP64; 1 = return the
                                last iterate with SKEW_EVD_WARN_REFINE */
     int debug;              /* SKEW_EVD_DEBUG_* bits (test hooks; 0 = none) */
-    int reserved[4];
+    int all_pairs;          /* 1: all n eigenpairs (both signs; see skew_evd_ex); 0 (default):
+                               the non-negative half */
+    int panel_method;       /* full-to-band panels: SKEW_EVD_PANEL_* (0 = auto: the autotuner's
+                               choice with opts.autotune, else a fixed rule by n) */
+    int reserved[2];
 } skew_evd_opts;
+
+/* Panel factorization of the full-to-band stage (Section 2.3.2). */
+#define SKEW_EVD_PANEL_AUTO 0
+#define SKEW_EVD_PANEL_CHOLQR 1      /* Cholesky QR twice + Householder reconstruction: a few
+                                        GEMM-shaped launches per panel (panels of fewer than b
+                                        rows use the Householder kernel) */
+#define SKEW_EVD_PANEL_HOUSEHOLDER 2 /* column-by-column Householder QR in one launch of
+                                        ceil(m/128) workgroups with a grid barrier per column */
 
 /* Debug bits of skew_evd_opts.debug (test hooks, not for production use). */
 #define SKEW_EVD_DEBUG_NAN_WS 1        /* fill the handle's workspace with NaN bytes (0xFF)
@@ -134,7 +148,7 @@ int skew_evd_destroy(skew_evd_handle h);
 /* The solver (Algorithm 1; Section 2.1 for the half spectrum).
  *   n        order of A (n >= 0)
  *   A        n x n, leading dimension lda >= max(1, n); strict lower triangle read
- *   nev      number of eigenpairs, 0 <= nev <= ceil(n/2)
+ *   nev      number of eigenpairs, 0 <= nev <= ceil(n/2) (nev = n with all_pairs)
  *   lambda   out, nev values: the nev smallest of the ceil(n/2) values
  *            lambda >= 0 of the spectrum {+-i lambda} (plus the exact 0 of odd
  *            n, returned as lambda[0] = 0), ascending
@@ -144,6 +158,12 @@ int skew_evd_destroy(skew_evd_handle h);
  *            -i lambda_k.  The phase of each z_k is unspecified.
  *   opts     NULL = defaults
  *   info     NULL or filled after the call's device work completed
+ * With opts->all_pairs = 1 (the "100 %" case of Section 4.1: every
+ * eigenvector) nev must be n: lambda[0..n) receives the whole spectrum as
+ * signed values mu_j ascending (A z_j = i mu_j z_j: -lambda_max .. -lambda_1,
+ * then the non-negative half, the exact 0 of odd n once) and column j of
+ * Z_re / Z_im the eigenvector of mu_j.  Only the non-negative half is
+ * computed; the vector of -lambda_k is conj(z_k), a copy.
  * skew_evd_ex is synchronous with respect to the handle's stream: it returns
  * after the results are in Z_re/Z_im/lambda.  Argument numbers for errors:
  * -2 n, -3 A, -4 lda, -5 nev, -6 lambda, -7 Z_re, -8 ldzr, -9 Z_im, -10 ldzi,
@@ -160,6 +180,10 @@ int skew_evd(int n, const double *A, int lda, int nev,
 
 /* Batched form: count independent problems (host arrays of per-problem sizes
  * and device pointers), each solved as by skew_evd_ex with ldz = n[i].
+ * Problems up to n = 4096 are solved together: their stages run side by side
+ * on 16 streams of the handle (HIP maps streams onto GPU_MAX_HW_QUEUES
+ * hardware queues per process, 4 unless the environment sets more; 16 lets
+ * them all run at once) and one bulge-chase launch serves all bands.
  * Only opts->precision = SKEW_EVD_PREC_FP64 is accepted (any other value
  * returns -10): the precision form is solved one problem at a time with
  * skew_evd_ex.
@@ -174,6 +198,38 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n,
                      double *const *lambda, double *const *Z_re,
                      double *const *Z_im, const skew_evd_opts *opts,
                      skew_evd_info *info, int *status);
+
+/* The Bethe-Salpeter eigenvalue problem through the skew-symmetric solver
+ * (Section 3, the four steps of the BSEPACK method; Theorem 2):
+ *   H_BS = [[A, B], [-conj(B), -conj(A)]],  A = A^H,  B = B^T  (m x m complex),
+ * definite ([[A, B], [conj(B), conj(A)]] > 0), so its eigenvalues are real
+ * pairs +-lambda.  Steps: M = [[Re(A+B), Im(A-B)], [-Im(A+B), Re(A-B)]]
+ * (Eq. SymmetricM, M = JH), Cholesky M = L L^T, eigenpairs of the skew-
+ * symmetric K = L^T J L (J = [[0, I], [-I, 0]]) by skew_evd_ex, and
+ * x = sqrt(lambda) Q L^{-T} z with Q = [[I, -iI], [I, iI]] / sqrt(2).
+ *   m        order of A and B (m >= 0); the problem has order 2m
+ *   A_re, A_im   real and imaginary planes of A (m x m, column-major, lda >= m);
+ *            the real plane is read in its lower triangle (diagonal included),
+ *            the imaginary plane entirely
+ *   B_re, B_im   the same for B (ldb >= m)
+ *   nev      0 <= nev <= m: the nev smallest positive eigenvalues
+ *   lambda   out, nev values, ascending
+ *   X_re, X_im   out, 2m x nev (ldx >= 2m): H_BS x_k = lambda_k x_k with the
+ *            BSE normalization x_k^H S x_k = 1, S = diag(I_m, -I_m); the
+ *            vector of -lambda_k is [conj(v); conj(u)] for x_k = [u; v]
+ *   opts     as for skew_evd_ex (precision, band, panel method, ...) for the
+ *            skew-symmetric eigenproblem; all_pairs must be 0
+ * Device pointers; synchronous with respect to h's stream; the handle holds a
+ * second workspace for M (then L), K and the back-transformation, about
+ * 8 (8 m^2 + 4 m nev + 4096 nev) bytes, grown on demand.
+ * Errors: -1 h, -2 m, -3 A_re, -4 A_im, -5 lda, -6 B_re, -7 B_im, -8 ldb,
+ * -9 nev, -10 lambda, -11 X_re, -12 X_im, -13 ldx, -14 opts;
+ * SKEW_EVD_ERR_NONFINITE (a NaN or Inf among the entries of M),
+ * SKEW_EVD_ERR_NOTDEF, or a status of skew_evd_ex. */
+int skew_evd_bse(skew_evd_handle h, int m, const double *A_re, const double *A_im, int lda,
+                 const double *B_re, const double *B_im, int ldb, int nev, double *lambda,
+                 double *X_re, double *X_im, int ldx, const skew_evd_opts *opts,
+                 skew_evd_info *info);
 
 /* Allocation-free solve, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -222,15 +278,16 @@ int skew_evd_tridiagonalize(skew_evd_handle h, int n, const double *A, int lda,
 int skew_evd_tridiag_eig(skew_evd_handle h, int n, const double *alpha, int nev,
                          double *lambda, double *Q, int ldq);
 
-/* Band-width autotuner (not in the paper; Section 4.1 notes how strongly the
- * speed of a reduction can depend on its block size).  Orders are grouped in
- * size classes of 128 (n in (128(c-1), 128c]).  On the first call for a class
- * and precision, a seeded synthetic skew matrix of order 128c (entries
- * (u - u')/2 with u, u' independent and uniform in [-1, 1)) is solved on h's
- * stream once per candidate band width {16, 32, 64}: one warm-up and three
- * timed calls each, host wall clock.  The fastest band is cached in h and
- * returned in *band; *ms (may be NULL) receives its best time per solve in
- * milliseconds.  Later calls for the class return the cached values without
+/* Band-width and panel-method autotuner (not in the paper; Section 4.1 notes
+ * how strongly the speed of a reduction can depend on its block size).  Orders
+ * are grouped in size classes of 128 (n in (128(c-1), 128c]).  On the first
+ * call for a class and precision, a seeded synthetic skew matrix of order 128c
+ * (entries (u - u')/2 with u, u' independent and uniform in [-1, 1)) is solved
+ * on h's stream once per candidate: band width {16, 32, 64} times panel method
+ * {SKEW_EVD_PANEL_CHOLQR, SKEW_EVD_PANEL_HOUSEHOLDER}, one warm-up and three
+ * timed calls each, host wall clock.  The fastest pair is cached in h (solves
+ * with opts.autotune use both); its band is returned in *band and *ms (may be
+ * NULL) receives its best time per solve in milliseconds.  Later calls for the class return the cached values without
  * solving.  Tuning allocates and frees its own device buffers (an input and
  * outputs of order 128c) and grows h's workspace.
  *   n          1 <= n <= SKEW_EVD_TUNE_NMAX

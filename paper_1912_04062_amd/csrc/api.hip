@@ -40,6 +40,7 @@ struct Plan {
     int n = 0, nev = 0, b = 0, nb2 = 0, prec = 0;
     int npanels = 0, ngroups = 0, nsig = 0;
     int orth_window = 0;
+    bool hh_panels = false;   // every panel by the Householder kernel (no Cholesky QR)
 };
 
 }  // namespace
@@ -61,6 +62,8 @@ struct skew_evd_handle_s {
     size_t kopen[SKEW_EVD_NKERN] = {};
     int refine_passes = 0;
     bool async = false;             // enqueue only: no stage events, no host waits (batched form)
+    char *ws2 = nullptr;            // Bethe-Salpeter route: M / L, K, back-transformation
+    size_t ws2_bytes = 0;
     bool noalloc = false;           // allocation-free entry point: fixed buffers, no events created
     double *lam_host = nullptr;     // pinned: eigenvalues, ||T||, then the polishing shifts
     size_t lam_cap = 0;
@@ -80,7 +83,11 @@ struct skew_evd_handle_s {
     char *bhost = nullptr;
     size_t bhost_cap = 0;
     // band-width autotuner: (precision, size class) -> (band, best wall ms)
-    std::map<int, std::pair<int, double>> tune;
+    struct Tuned {
+        int band, panel;
+        double ms;
+    };
+    std::map<int, Tuned> tune;
 };
 
 namespace {
@@ -201,9 +208,16 @@ int auto_band(int n)
     return 16;
 }
 
-Plan make_plan(int n, int nev, int b, int prec)
+// Fixed panel rule (opts.panel_method = 0 without the autotuner): Cholesky QR
+// everywhere.  (Householder panels for every order up to 1024 made the batch
+// of 512 uneven problems slower, 1.76 s against 1.19 s: the autotuner picks
+// them per size class only where they win.)
+constexpr int HH_PANEL_NMAX = 0;
+
+Plan make_plan(int n, int nev, int b, int prec, int panel = SKEW_EVD_PANEL_AUTO)
 {
     Plan p;
+    p.hh_panels = panel == SKEW_EVD_PANEL_HOUSEHOLDER || (panel == SKEW_EVD_PANEL_AUTO && n <= HH_PANEL_NMAX);
     p.n = n;
     p.nev = nev;
     p.prec = prec;
@@ -354,7 +368,7 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
         double *tauj = ptr<double>(h, L.tauall) + (size_t)j * b;
         HCHK(kt_begin(h, SKEW_EVD_K_PANEL));
         const unsigned *skip = nullptr;
-        if (m >= b) {
+        if (m >= b && !p.hh_panels) {
             // Cholesky QR twice + Householder reconstruction (Gram matrices
             // and the small factorizations in FP64 also in the FP32 form); the
             // Householder panel kernel below runs only when this path flags
@@ -785,6 +799,8 @@ int validate_opts(const skew_evd_opts *o)
     if (o->max_refine_sweeps < 0) return 1;
     if (o->no_fp64_fallback != 0 && o->no_fp64_fallback != 1) return 1;
     if (o->debug & ~(SKEW_EVD_DEBUG_NAN_WS | SKEW_EVD_DEBUG_ZERO_WS | SKEW_EVD_DEBUG_INVIT_NOCONV)) return 1;
+    if (o->all_pairs != 0 && o->all_pairs != 1) return 1;
+    if (o->panel_method < SKEW_EVD_PANEL_AUTO || o->panel_method > SKEW_EVD_PANEL_HOUSEHOLDER) return 1;
     return 0;
 }
 
@@ -880,7 +896,7 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     // the refinement works on the whole invariant half: the precision form
     // always computes ceil(n/2) pairs and returns the first nev
     if (prec) nev = (n + 1) / 2;
-    Plan p = make_plan(n, nev, o.band, prec);
+    Plan p = make_plan(n, nev, o.band, prec, o.panel_method);
     Layout L = plan_layout(p);
     int rc = ensure_ws(h, L.total, o.workspace_limit);
     if (rc) return rc;
@@ -1008,6 +1024,7 @@ int skew_evd_destroy(skew_evd_handle h)
     if (!h) return -1;
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
+    if (h->ws2) (void)hipFree(h->ws2);
     for (int i = 0; i < NSTAGE_EV; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->ctl_host) (void)hipHostFree(h->ctl_host);
@@ -1069,13 +1086,14 @@ void tune_matrix(int n, std::vector<double> &A)
         }
 }
 
-int tune_band(skew_evd_handle h, int n, int precision, size_t wslimit, int *band, double *ms)
+int tune_band(skew_evd_handle h, int n, int precision, size_t wslimit, int *band, double *ms, int *panel = nullptr)
 {
     const int key = precision * 65536 + tune_class(n);
     auto it = h->tune.find(key);
     if (it != h->tune.end()) {
-        *band = it->second.first;
-        if (ms) *ms = it->second.second;
+        *band = it->second.band;
+        if (panel) *panel = it->second.panel;
+        if (ms) *ms = it->second.ms;
         return SKEW_EVD_OK;
     }
     const int nr = tune_class(n) * TUNE_CLASS;
@@ -1100,15 +1118,18 @@ int tune_band(skew_evd_handle h, int n, int precision, size_t wslimit, int *band
         set_hip_error(e, "autotune input copy");
         rc = SKEW_EVD_ERR_HIP;
     }
-    int best_b = 0, last_err = SKEW_EVD_OK;
+    int best_b = 0, best_p = SKEW_EVD_PANEL_CHOLQR, last_err = SKEW_EVD_OK;
     double best_ms = 0.0;
-    for (int c = 0; rc == SKEW_EVD_OK && c < (int)(sizeof(TUNE_CAND) / sizeof(int)); ++c) {
-        const int b = TUNE_CAND[c];
+    const int ncand = (int)(sizeof(TUNE_CAND) / sizeof(int));
+    for (int c = 0; rc == SKEW_EVD_OK && c < 2 * ncand; ++c) {
+        const int b = TUNE_CAND[c % ncand];
+        const int pm = c < ncand ? SKEW_EVD_PANEL_CHOLQR : SKEW_EVD_PANEL_HOUSEHOLDER;
         if (b > nr - 2) continue;
         skew_evd_opts o;
         skew_evd_default_opts(&o);
         o.precision = precision;
         o.band = b;
+        o.panel_method = pm;
         o.workspace_limit = wslimit;
         double tmin = 0.0;
         int crc = SKEW_EVD_OK;
@@ -1125,6 +1146,7 @@ int tune_band(skew_evd_handle h, int n, int precision, size_t wslimit, int *band
         }
         if (best_b == 0 || tmin < best_ms) {
             best_b = b;
+            best_p = pm;
             best_ms = tmin;
         }
     }
@@ -1135,8 +1157,9 @@ int tune_band(skew_evd_handle h, int n, int precision, size_t wslimit, int *band
     (void)hipFree(dzi);
     if (rc) return rc;
     if (best_b == 0) return last_err ? last_err : SKEW_EVD_ERR_NOCONV;
-    h->tune[key] = {best_b, best_ms};
+    h->tune[key] = {best_b, best_p, best_ms};
     *band = best_b;
+    if (panel) *panel = best_p;
     if (ms) *ms = best_ms;
     return SKEW_EVD_OK;
 }
@@ -1158,7 +1181,8 @@ int skew_evd_ex(skew_evd_handle h, int n, const double *A, int lda, int nev, dou
     if (n < 0) return -2;
     if (n > 0 && !A) return -3;
     if (lda < std::max(1, n)) return -4;
-    if (nev < 0 || nev > (n + 1) / 2) return -5;
+    const bool all = opts && opts->all_pairs == 1;
+    if (all ? nev != n : (nev < 0 || nev > (n + 1) / 2)) return -5;
     if (nev > 0 && !lambda) return -6;
     if (nev > 0 && !Z_re) return -7;
     if (ldzr < std::max(1, n)) return -8;
@@ -1169,12 +1193,25 @@ int skew_evd_ex(skew_evd_handle h, int n, const double *A, int lda, int nev, dou
     if (n == 0 || nev == 0) return SKEW_EVD_OK;
     skew_evd_opts tuned;
     if (opts && opts->autotune && opts->band == 0 && n <= SKEW_EVD_TUNE_NMAX) {
-        int b = 0;
-        int rc = tune_band(h, n, opts->precision, opts->workspace_limit, &b, nullptr);
+        int b = 0, pm = SKEW_EVD_PANEL_AUTO;
+        int rc = tune_band(h, n, opts->precision, opts->workspace_limit, &b, nullptr, &pm);
         if (rc) return rc;
         tuned = *opts;
         tuned.band = b;
+        if (tuned.panel_method == SKEW_EVD_PANEL_AUTO) tuned.panel_method = pm;
         opts = &tuned;
+    }
+    if (all) {
+        // the non-negative half into the last ceil(n/2) columns, then the
+        // conjugates of its positive values into the first n - ceil(n/2)
+        const int half = (n + 1) / 2, off = n - half;
+        int rc = solve(h, n, A, lda, half, lambda + off, Z_re + (size_t)off * ldzr, ldzr, Z_im + (size_t)off * ldzi,
+                       ldzi, opts, info);
+        if (rc != SKEW_EVD_OK && rc != SKEW_EVD_WARN_REFINE) return rc;
+        skew::launch_mirror(Z_re, ldzr, Z_im, ldzi, lambda, n, off, h->stream);
+        HCHK(hipGetLastError());
+        HCHK(hipStreamSynchronize(h->stream));
+        return rc;
     }
     return solve(h, n, A, lda, nev, lambda, Z_re, ldzr, Z_im, ldzi, opts, info);
 }
@@ -1232,7 +1269,7 @@ namespace {
 // eigenvectors need the polishing step, planned on the host), are solved one
 // by one afterwards.
 constexpr int BATCH_NMAX = 4096;
-constexpr int BATCH_STREAMS = 8;
+constexpr int BATCH_STREAMS = 16;
 constexpr int CHASE_LANES = 64;
 
 struct BatchItem {
@@ -1332,7 +1369,7 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
     for (int k = 0; k < cnt; ++k) {
         const int i = ids[k];
         it[k].idx = i;
-        it[k].p = make_plan(n[i], nev[i], popt[i].band, 0);
+        it[k].p = make_plan(n[i], nev[i], popt[i].band, 0, popt[i].panel_method);
         it[k].L = plan_layout(it[k].p);
         it[k].off = off;
         off += it[k].L.total;
@@ -1492,14 +1529,15 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
         if (opts) popt[i] = *opts;
         else skew_evd_default_opts(&popt[i]);
         if (popt[i].autotune && popt[i].band == 0 && n[i] >= 1 && n[i] <= SKEW_EVD_TUNE_NMAX) {
-            int b = 0;
-            int rc = tune_band(h, n[i], popt[i].precision, popt[i].workspace_limit, &b, nullptr);
+            int b = 0, pm = SKEW_EVD_PANEL_AUTO;
+            int rc = tune_band(h, n[i], popt[i].precision, popt[i].workspace_limit, &b, nullptr, &pm);
             if (rc) {
                 // nothing was solved: every problem reports the tuner's status
                 for (int k = 0; k < count; ++k) status[k] = rc;
                 return rc;
             }
             popt[i].band = b;
+            if (popt[i].panel_method == SKEW_EVD_PANEL_AUTO) popt[i].panel_method = pm;
         }
         popt[i].autotune = 0;
     }
@@ -1608,6 +1646,82 @@ int skew_evd_noalloc(int n, const double *A, int lda, int nev, double *lambda, d
     return solve(&sl.h, n, A, lda, nev, lambda, Z_re, ldzr, Z_im, ldzi, &o, nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// The Bethe-Salpeter route (Section 3): M, Cholesky, the skew eigenproblem of
+// L^T J L through solve(), and the back-transformation of its vectors.
+int skew_evd_bse(skew_evd_handle h, int m, const double *A_re, const double *A_im, int lda, const double *B_re,
+                 const double *B_im, int ldb, int nev, double *lambda, double *X_re, double *X_im, int ldx,
+                 const skew_evd_opts *opts, skew_evd_info *info)
+{
+    if (!h) return -1;
+    if (m < 0) return -2;
+    if (m > 0 && !A_re) return -3;
+    if (m > 0 && !A_im) return -4;
+    if (lda < std::max(1, m)) return -5;
+    if (m > 0 && !B_re) return -6;
+    if (m > 0 && !B_im) return -7;
+    if (ldb < std::max(1, m)) return -8;
+    if (nev < 0 || nev > m) return -9;
+    if (nev > 0 && !lambda) return -10;
+    if (nev > 0 && !X_re) return -11;
+    if (nev > 0 && !X_im) return -12;
+    if (ldx < std::max(1, 2 * m)) return -13;
+    if (validate_opts(opts) || (opts && opts->all_pairs)) return -14;
+    if (info) memset(info, 0, sizeof(*info));
+    if (m == 0 || nev == 0) return SKEW_EVD_OK;
+    const int n = 2 * m;
+    const size_t nblk = (n + 63) / 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += al(bytes);
+        return o;
+    };
+    const size_t oM = take(sizeof(double) * (size_t)n * n), oK = take(sizeof(double) * (size_t)n * n),
+                 oR = take(sizeof(double) * nblk * 64 * 64), oZ = take(sizeof(double) * (size_t)n * 2 * nev),
+                 oW = take(sizeof(double) * (size_t)tn_parts_max() * 64 * 2 * nev), oF = take(sizeof(unsigned) * 4);
+    const size_t limit = opts ? opts->workspace_limit : 0;
+    if (limit && off > limit) {
+        snprintf(g_errtext, sizeof(g_errtext), "workspace of %zu bytes exceeds the limit of %zu", off, limit);
+        return SKEW_EVD_ERR_NOMEM;
+    }
+    if (off > h->ws2_bytes) {
+        HCHK(hipStreamSynchronize(h->stream));
+        if (h->ws2) HCHK(hipFree(h->ws2));
+        h->ws2 = nullptr;
+        h->ws2_bytes = 0;
+        if (hipMalloc((void **)&h->ws2, off) != hipSuccess) {
+            (void)hipGetLastError();
+            h->ws2 = nullptr;
+            snprintf(g_errtext, sizeof(g_errtext), "hipMalloc of %zu bytes failed", off);
+            return SKEW_EVD_ERR_NOMEM;
+        }
+        h->ws2_bytes = off;
+    }
+    hipStream_t st = h->stream;
+    double *M = (double *)(h->ws2 + oM), *K = (double *)(h->ws2 + oK), *Rinv = (double *)(h->ws2 + oR),
+           *Z = (double *)(h->ws2 + oZ), *Wp = (double *)(h->ws2 + oW);
+    unsigned *flags = (unsigned *)(h->ws2 + oF);
+    skew::launch_fill32(flags, 0u, 4, st);
+    skew::launch_bse_build_m(A_re, A_im, lda, B_re, B_im, ldb, m, M, n, flags, st);
+    skew::launch_cholesky(M, n, n, Rinv, flags, st);
+    HCHK(hipGetLastError());
+    unsigned hf[4] = {0, 0, 0, 0};
+    HCHK(hipMemcpyAsync(hf, flags, sizeof(unsigned) * 4, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    if (hf[0] & 1u) return SKEW_EVD_ERR_NONFINITE;
+    if (hf[0] & 4u) return SKEW_EVD_ERR_NOTDEF;
+    skew::launch_ltjl(M, n, m, K, n, st);
+    HCHK(hipGetLastError());
+    int rc = solve(h, n, K, n, nev, lambda, Z, n, Z + (size_t)n * nev, n, opts, info);
+    if (rc != SKEW_EVD_OK && rc != SKEW_EVD_WARN_REFINE) return rc;
+    skew::launch_trsm_lt(M, n, n, Rinv, Z, n, 2 * nev, Wp, st);
+    skew::launch_bse_x(Z, n, m, nev, lambda, X_re, X_im, ldx, st);
+    HCHK(hipGetLastError());
+    HCHK(hipStreamSynchronize(st));
+    return rc;
+}
+
 int skew_evd_band_reduce(skew_evd_handle h, int n, const double *A, int lda, int b, double *band, int ldband)
 {
     if (!h) return -1;
@@ -1695,6 +1809,7 @@ const char *skew_evd_status_string(int status)
     case SKEW_EVD_ERR_NOMEM: return g_errtext[0] ? g_errtext : "out of device memory";
     case SKEW_EVD_ERR_HIP: return g_errtext[0] ? g_errtext : "HIP runtime error";
     case SKEW_EVD_ERR_NODEVICE: return "no usable HIP device";
+    case SKEW_EVD_ERR_NOTDEF: return "the Bethe-Salpeter matrix is not definite (Cholesky of M failed)";
     default: return status < 0 ? "invalid argument" : "unknown status";
     }
 }

@@ -908,6 +908,19 @@ void launch_reduce_left(const double *S0, const double *Cpart, int S, int M, int
     hipLaunchKernelGGL(k_reduce_left, dim3(N), dim3(256), shm, st, S0, Cpart, S, M, N, out);
 }
 
+// Whole-spectrum output: columns c < off get the conjugate of column n-1-c
+// (the eigenvector of -lambda is conj(z) of +lambda), lambda[c] = -lambda[n-1-c].
+__global__ void k_mirror(double *__restrict__ Zr, int ldr, double *__restrict__ Zi, int ldi,
+                         double *__restrict__ lam, int n, int off)
+{
+    const int c = blockIdx.y, src = n - 1 - c;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        Zr[(size_t)c * ldr + i] = Zr[(size_t)src * ldr + i];
+        Zi[(size_t)c * ldi + i] = -Zi[(size_t)src * ldi + i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) lam[c] = -lam[src];
+}
+
 template <typename T>
 void launch_copy_cols(const T *src, int lds, T *dst, int ldd, int m, int ncol, hipStream_t st)
 {
@@ -993,6 +1006,13 @@ template void launch_gemm_nn<double>(const double *, int, const double *, int, i
                                      int, hipStream_t);
 template void launch_gemm_nn<float>(const float *, int, const double *, int, int, int, int, float *, int, double,
                                     int, hipStream_t);
+void launch_mirror(double *Zr, int ldr, double *Zi, int ldi, double *lam, int n, int off, hipStream_t st)
+{
+    if (off <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_mirror, dim3(cdiv(n, 256) > 8 ? 8 : cdiv(n, 256), off), dim3(256), 0, st, Zr, ldr, Zi, ldi,
+                       lam, n, off);
+}
+
 template void launch_copy_cols<double>(const double *, int, double *, int, int, int, hipStream_t);
 template void launch_copy_cols<float>(const float *, int, float *, int, int, int, hipStream_t);
 template void launch_to_double<double>(const double *, int, double *, int, int, int, hipStream_t);

@@ -127,10 +127,13 @@ __global__ __launch_bounds__(256) void k_bulge_chase(skew::ChaseProb one, const 
             }
         }
         __syncthreads();
-        if (p_next == -2) break;
-        if (p_next == -3) continue;
-        const int s = s_next;
-        const skew::ChaseProb P = (p_next >= 0) ? probs[p_next] : one;
+        // the same in every lane: made explicit so that the problem's
+        // parameters and addresses stay scalar
+        const int pn = __builtin_amdgcn_readfirstlane(p_next);
+        const int s = __builtin_amdgcn_readfirstlane(s_next);
+        if (pn == -2) break;
+        if (pn == -3) continue;
+        const skew::ChaseProb P = (pn >= 0) ? probs[pn] : one;
         double *__restrict__ ab = P.ab;
         double *__restrict__ V2 = P.V2;
         double *__restrict__ tau2 = P.tau2;
@@ -371,7 +374,8 @@ int chase_ngroups(int n, int b, int nb2, int *goff_host)
 
 // Workgroups of the bulge-chase launch: enough for the sweeps that can be in
 // flight at once (a sweep of n/b steps starts about every second step of its
-// predecessor), never more than the device holds.
+// predecessor, so about n/(2b) are in flight) with room to spare, so that a
+// sweep never waits for a free workgroup; never more than the device holds.
 int chase_workgroups(int n, int b)
 {
     int dev = 0, ncu = 256;
@@ -381,7 +385,7 @@ int chase_workgroups(int n, int b)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_bulge_chase, 256, 0);
     if (occ < 1) occ = 1;
     int G = ncu * occ;
-    const int inflight = (n / (b > 0 ? b : 1)) / 2 + 16;
+    const int inflight = n / (b > 0 ? b : 1) + 16;
     if (G > inflight) G = inflight;
     if (G > n - 2) G = n - 2;
     if (G < 1) G = 1;

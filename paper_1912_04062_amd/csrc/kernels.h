@@ -91,6 +91,8 @@ void launch_reduce_left(const double *S0, const double *Cpart, int S, int M, int
 template <typename T>
 void launch_copy_cols(const T *src, int lds, T *dst, int ldd, int m, int ncol, hipStream_t st);
 void launch_to_float(const double *src, int lds, float *dst, int ldd, int m, int ncol, hipStream_t st);
+// columns c < off <- conj(column n-1-c), lam[c] = -lam[n-1-c] (whole-spectrum output)
+void launch_mirror(double *Zr, int ldr, double *Zi, int ldi, double *lam, int n, int off, hipStream_t st);
 template <typename T>
 void launch_to_double(const T *src, int lds, double *dst, int ldd, int m, int ncol, hipStream_t st);
 
@@ -103,6 +105,20 @@ template <typename T>
 void launch_bt1_block(T *Z, int ldz, int r0, int m, int ncols, const T *V1, int b1, const T *V2, int m2,
                       const double *Tm, int KK, double *Wp, T *W2, hipStream_t st);
 void launch_merge_t(const double *T1, const double *T2, const double *Gp, int S, int b, double *Tm, hipStream_t st);
+
+// bse.hip (the Bethe-Salpeter route)
+void launch_bse_build_m(const double *Ar, const double *Ai, int lda, const double *Br, const double *Bi, int ldb,
+                        int m, double *M, int ldm, unsigned *flags, hipStream_t st);
+// blocked Cholesky of the lower triangle of M (n x n) in place; R^{-1} of each
+// diagonal block (64 x 64) into Rinv_all; bit 4 of *flags when M is not
+// positive definite
+void launch_cholesky(double *M, int ldm, int n, double *Rinv_all, unsigned *flags, hipStream_t st);
+void launch_ltjl(const double *L, int ldl, int m, double *K, int ldk, hipStream_t st);
+// Z <- L^{-T} Z (n x ncols), Wp: tn_parts_max x 64 x ncols doubles
+void launch_trsm_lt(const double *L, int ldl, int n, const double *Rinv_all, double *Z, int ldz, int ncols,
+                    double *Wp, hipStream_t st);
+void launch_bse_x(const double *Z, int ldz, int m, int nev, const double *lam, double *Xr, double *Xi, int ldx,
+                  hipStream_t st);
 
 // refine.hip
 template <typename T>

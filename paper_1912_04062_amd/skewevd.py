@@ -23,6 +23,7 @@ WARN_REFINE = 3
 ERR_NOMEM = 4
 ERR_HIP = 5
 ERR_NODEVICE = 6
+ERR_NOTDEF = 7
 
 PREC_FP64 = 0
 PREC_FP32_REFINE = 1
@@ -38,7 +39,8 @@ class Opts(ctypes.Structure):
                 ("max_refine_sweeps", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("workspace_limit", ctypes.c_size_t), ("profile", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("no_fp64_fallback", ctypes.c_int),
-                ("debug", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("debug", ctypes.c_int), ("all_pairs", ctypes.c_int), ("panel_method", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class KStat(ctypes.Structure):
@@ -115,6 +117,9 @@ def _load():
     lib.skew_evd_version.restype = ip
     lib.skew_evd_noalloc.argtypes = [ip, vp, ip, ip, vp, vp, ip, vp, ip, vp]
     lib.skew_evd_noalloc.restype = ip
+    lib.skew_evd_bse.argtypes = [vp, ip, vp, vp, ip, vp, vp, ip, ip, vp, vp, vp, ip, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(Info)]
+    lib.skew_evd_bse.restype = ip
     _lib = lib
     return lib
 
@@ -128,7 +133,8 @@ def status_string(status):
 
 
 def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=None,
-                 workspace_limit=0, profile=0, autotune=0, no_fp64_fallback=0, debug=0):
+                 workspace_limit=0, profile=0, autotune=0, no_fp64_fallback=0, debug=0, all_pairs=0,
+                 panel_method=0):
     o = Opts()
     _load().skew_evd_default_opts(ctypes.byref(o))
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
@@ -142,6 +148,8 @@ def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=No
     o.autotune = int(autotune)
     o.no_fp64_fallback = int(no_fp64_fallback)
     o.debug = int(debug)
+    o.all_pairs = int(all_pairs)
+    o.panel_method = int(panel_method)
     return o
 
 
@@ -213,6 +221,9 @@ class Handle:
         """
         n = A.shape[0]
         half = (n + 1) // 2
+        o = opts if opts is not None else default_opts(precision, band, profile=profile)
+        if o.all_pairs:
+            nev = n                      # every eigenpair, both signs
         nev = half if nev is None else int(nev)
         Ac, lda = colmajor(A)
         dev = A.device
@@ -222,7 +233,6 @@ class Handle:
             zi = empty_colmajor(max(n, 1), max(nev, 1), dev)
         else:
             lam, zr, zi = out
-        o = opts if opts is not None else default_opts(precision, band, profile=profile)
         inf = info if info is not None else Info()
         st = self._lib.skew_evd_ex(self._h, n, ctypes.c_void_p(Ac.data_ptr()), lda, nev,
                                    ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(zr.data_ptr()),
@@ -274,6 +284,32 @@ class Handle:
         self.last_info = inf
         res = [(lm[:v], zr[:x, :v], zi[:x, :v]) for (lm, zr, zi), x, v in zip(outs, ns, nevs)]
         return res, [status[i] for i in range(count)], st
+
+    def bse(self, A, B, nev=None, opts=None, check=True):
+        """Bethe-Salpeter eigenpairs of H_BS = [[A, B], [-conj(B), -conj(A)]]
+        (A Hermitian, B complex symmetric, complex128 CUDA tensors, m x m).
+        Returns (lam, X): the nev smallest positive eigenvalues and the
+        eigenvectors x_k (2m x nev complex, x^H S x = 1)."""
+        m = A.shape[0]
+        nev = m if nev is None else int(nev)
+        planes = [colmajor(t)[0] for t in (A.real, A.imag, B.real, B.imag)]
+        dev = A.device
+        lam = torch.empty(max(nev, 1), dtype=torch.float64, device=dev)
+        xr = empty_colmajor(max(2 * m, 1), max(nev, 1), dev)
+        xi = empty_colmajor(max(2 * m, 1), max(nev, 1), dev)
+        o = opts if opts is not None else default_opts()
+        inf = Info()
+        st = self._lib.skew_evd_bse(self._h, m, ctypes.c_void_p(planes[0].data_ptr()),
+                                    ctypes.c_void_p(planes[1].data_ptr()), planes[0].stride(1),
+                                    ctypes.c_void_p(planes[2].data_ptr()), ctypes.c_void_p(planes[3].data_ptr()),
+                                    planes[2].stride(1), nev, ctypes.c_void_p(lam.data_ptr()),
+                                    ctypes.c_void_p(xr.data_ptr()), ctypes.c_void_p(xi.data_ptr()),
+                                    xr.stride(1), ctypes.byref(o), ctypes.byref(inf))
+        self.last_status = st
+        self.last_info = inf
+        if check and st not in (OK, WARN_REFINE):
+            raise SkewEvdError(st, "skew_evd_bse")
+        return lam[:nev], torch.complex(xr[:2 * m, :nev].contiguous(), xi[:2 * m, :nev].contiguous())
 
     # -- stage entry points --------------------------------------------------
     def band_reduce(self, A, b):

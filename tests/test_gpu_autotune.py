@@ -3,7 +3,8 @@
 The tuner only chooses among supported band widths, so its results are checked
 like any other solve: against the oracle (eigenvalues within 1e-12 ||A||) and
 by residual and orthogonality (1e-13), and bitwise against a single solve with
-the same band width (same kernels, same tile configuration).
+the same tuned configuration (band width and panel method: same kernels, same
+tiles).
 """
 import numpy as np
 import pytest
@@ -65,6 +66,7 @@ def test_ex_autotune_takes_the_tuned_band(h):
 
 def test_batched_autotuned_matches_oracle_and_single_solves(h):
     import torch
+    from paper_1912_04062_amd import skewevd
     rng = np.random.default_rng(5)
     sizes = [int(x) for x in rng.integers(64, 512, size=10, endpoint=True)]
     sizes += [65, 129]            # odd orders: the exact zero eigenvalue
@@ -79,7 +81,9 @@ def test_batched_autotuned_matches_oracle_and_single_solves(h):
         lam = lam.cpu().numpy()
         zr = zr.cpu().numpy()
         zi = zi.cpu().numpy()
-        l1, z1r, z1i = h.solve(to_dev(A), band=b)
+        # a single solve with the same tuned configuration (band and panel method)
+        l1, z1r, z1i = h.solve(to_dev(A), opts=skewevd.default_opts(autotune=1))
+        assert h.last_info.band == b
         assert np.array_equal(lam, l1.cpu().numpy())
         assert np.array_equal(zr, z1r.cpu().numpy()) and np.array_equal(zi, z1i.cpu().numpy())
         lref, _ = oracle.skew_evd(A)

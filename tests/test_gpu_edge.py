@@ -187,3 +187,53 @@ def test_batched_mixed_problems(h):
         if A.shape[0] > 1:
             c = dev_checks(Ad, lam, zr, zi, nA=max(lam.max().item(), 1.0))
             assert c["colres"] <= 1e-12 and c["orth_max"] <= 1e-12, (k, c)
+
+
+@pytest.mark.parametrize("n,precision", [(300, "fp64"), (301, "fp64"), (257, "fp32")])
+def test_all_pairs(h, n, precision):
+    """opts.all_pairs: every eigenpair of both signs, ascending, the exact zero
+    of odd n once; the n vectors are orthonormal (conj(z) of +lambda is the
+    vector of -lambda, orthogonal to z) and match the oracle's spectrum."""
+    import oracle
+    import torch
+    from paper_1912_04062_amd import skewevd
+    print(f"all pairs n={n} {precision}", flush=True)
+    A = wl.random_skew(n, 600 + n)
+    o = skewevd.default_opts(precision, all_pairs=1)
+    mu, zr, zi = h.solve(to_dev(A), opts=o)
+    torch.cuda.synchronize()
+    mu = mu.cpu().numpy()
+    Z = zr.cpu().numpy() + 1j * zi.cpu().numpy()
+    assert mu.shape == (n,) and Z.shape == (n, n)
+    lref, _ = oracle.skew_evd(A)
+    full = np.concatenate([-lref[::-1][: n - len(lref)], lref])
+    nA = lref.max()
+    assert np.all(np.diff(mu) >= 0)
+    assert np.max(np.abs(mu - full)) <= TOL_EIG * nA
+    if n % 2:
+        assert mu[n // 2] == 0.0
+    assert np.array_equal(mu[: n // 2], -mu[::-1][: n // 2])
+    res, orth, _ = metrics(A, mu, Z, nA)
+    print(f"  res={res:.2e} orth={orth:.2e}", flush=True)
+    assert res <= TOL_RES and orth <= TOL_ORTH
+
+
+@pytest.mark.parametrize("n,pm", [(300, 1), (300, 2), (1100, 1), (1100, 2), (2049, 2)])
+def test_panel_methods(h, n, pm):
+    """Both panel factorizations of the full-to-band stage (Cholesky QR twice
+    with reconstruction, and the column-by-column Householder kernel) give
+    eigenpairs within the FP64 tolerances of the oracle."""
+    import oracle
+    import torch
+    from paper_1912_04062_amd import skewevd
+    print(f"panel method {pm} n={n}", flush=True)
+    A = wl.random_skew(n, 900 + n)
+    lam, zr, zi = h.solve(to_dev(A), opts=skewevd.default_opts(panel_method=pm))
+    torch.cuda.synchronize()
+    lam = lam.cpu().numpy()
+    Z = zr.cpu().numpy() + 1j * zi.cpu().numpy()
+    lref, _ = oracle.skew_evd(A)
+    nA = lref.max()
+    assert np.max(np.abs(lam - lref)) <= TOL_EIG * nA
+    res, orth, _ = metrics(A, lam, Z, nA)
+    assert res <= TOL_RES and orth <= TOL_ORTH
