@@ -262,6 +262,10 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--nev", type=int, default=0,
                     help="eigenpairs (0 = n/2, the headline); fewer for a partial-spectrum line")
+    ap.add_argument("--reduction", default="two", choices=["two", "one", "complex"],
+                    help="two-stage (the headline), the one-stage reduction of Section 2.3.1 "
+                         "(FP64; for the one- vs two-stage comparison), or the complex Hermitian "
+                         "route on iA (FP64; the complex-arithmetic comparison)")
     ap.add_argument("--all-pairs", action="store_true",
                     help="all n eigenpairs of both signs (the 100 %% case; the other half is a copy)")
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32", "both"])
@@ -314,6 +318,8 @@ def main():
            skewevd.empty_colmajor(n, nout, "cuda"), skewevd.empty_colmajor(n, nout, "cuda"))
     F = useful_flops(n, (n + 1) // 2 if args.all_pairs else nev)
     forms = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
+    if args.reduction != "two":
+        forms = ["fp64"]            # the one-stage routes are FP64 only
     results = {}
     warm = max(args.warmup, 1)      # at least one untimed run (it also names the dominant kernel)
     for form in forms:
@@ -323,7 +329,8 @@ def main():
         # the timers of the many small launches stay out of the timed region
         full = None
         def opts(prof):
-            return skewevd.default_opts(form, profile=prof, all_pairs=int(args.all_pairs))
+            return skewevd.default_opts(form, profile=prof, all_pairs=int(args.all_pairs),
+                                        reduction=args.reduction)
         for w in range(warm):
             h.solve(Ad, nev=nev, out=out, opts=opts(1))
             full = h.last_info.as_dict()
@@ -371,6 +378,10 @@ def main():
                           "bt1": "k_bt1_w + k_bt1_t + k_bt1_z", "tridiag": "k_bisect + k_invit + orthogonalization",
                           "skew_symm_w": "k_skew_symm + k_gram + k_small + k_wform",
                           "skew_syr2k": "k_skew_syr2k", "refine": "refinement kernels"}.get(dom, dom)
+    if args.reduction == "one" and dom == "panel_qr":
+        roof["gpu_kernel"] = "k_os_col + k_os_symv + k_os_dots + k_os_w + k_skew_syr2k (one-stage reduction)"
+    if args.reduction == "complex" and dom == "panel_qr":
+        roof["gpu_kernel"] = "k_h_col + k_h_hemv + k_h_dots + k_h_w + k_her2k (complex Hermitian reduction)"
     roof["launches_per_step"] = kinfo["launches"]
     roof["ms_per_step"] = kern[dom]
     roof["kernels_ms"] = results[best]["kernels_untimed"]   # from an untimed run with every kernel timed
@@ -383,9 +394,11 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": f"dense random skew-symmetric A=(B-B^T)/2, B iid N(0,1), seed 4, "
-                               f"n={n}, nev={nev}{' (all n pairs)' if args.all_pairs else ''}; "
+                               f"n={n}, nev={nev}{' (all n pairs)' if args.all_pairs else ''}"
+                               f"{ {'two': '', 'one': '; one-stage reduction', 'complex': '; complex Hermitian route on iA'}[args.reduction] }; "
                                f"reported form: {best}",
-                   "n": n, "nev": nev, "all_pairs": bool(args.all_pairs), "precision": best,
+                   "n": n, "nev": nev, "all_pairs": bool(args.all_pairs), "reduction": args.reduction,
+                   "precision": best,
                    "band": infos[0]["band"], "useful_flops": F},
         "forms": form_summary,
         "stages_ms": stage_avg,

@@ -81,8 +81,34 @@ typedef struct skew_evd_opts {
                                the non-negative half */
     int panel_method;       /* full-to-band panels: SKEW_EVD_PANEL_* (0 = auto: the autotuner's
                                choice with opts.autotune, else a fixed rule by n) */
-    int reserved[2];
+    int reduction;          /* SKEW_EVD_REDUCE_TWO_STAGE (default), SKEW_EVD_REDUCE_ONE_STAGE or
+                               SKEW_EVD_REDUCE_COMPLEX_HERMITIAN */
+    int reserved[1];
 } skew_evd_opts;
+
+/* Reduction to tridiagonal form.  TWO_STAGE: full-to-band, then bulge chasing
+ * (Section 2.3.2, the ELPA2 route).  ONE_STAGE (Section 2.3.1, the ELPA1 route
+ * that the paper's GPU variant offloads): Householder reflectors column by
+ * column, each needing a skew matrix-vector product with the whole trailing
+ * matrix (streamed from HBM), the rank-2 updates of a panel of 64 columns
+ * deferred to one skew rank-128 update; FP64 only, band must be 0; its
+ * back-transformation is one stage of 64-reflector compact-WY blocks. */
+#define SKEW_EVD_REDUCE_TWO_STAGE 0
+#define SKEW_EVD_REDUCE_ONE_STAGE 1
+/* COMPLEX_HERMITIAN: the comparison route of the paper's introduction and
+ * Section 4.1 (Table 1): the Hermitian matrix H = iA is solved with complex
+ * arithmetic as a general complex Hermitian eigensolver would, without using
+ * its structure: one-stage complex Householder tridiagonalization (H held as
+ * real and imaginary planes of its lower triangle; reflectors H_c = I - tau v v^H
+ * with complex tau and real beta, so the tridiagonal matrix is real), the
+ * eigenpairs of index floor(n/2) .. floor(n/2) + nev - 1 in ascending order of
+ * that real symmetric tridiagonal matrix with its diagonal (for iA these are
+ * the non-negative half, H x = lambda x), and the back-transformation by
+ * complex compact-WY blocks of 64 reflectors.  The results are returned in the
+ * skew solver's form: lambda and z = conj(x), A z = i lambda z.  FP64 only,
+ * band must be 0.  The workspace holds both planes of H: twice the skew
+ * routes' n x n. */
+#define SKEW_EVD_REDUCE_COMPLEX_HERMITIAN 2
 
 /* Panel factorization of the full-to-band stage (Section 2.3.2). */
 #define SKEW_EVD_PANEL_AUTO 0
@@ -100,7 +126,7 @@ typedef struct skew_evd_opts {
                                           vector: the tridiagonal solve reports NOCONV */
 
 /* Main kernels, for the per-kernel statistics of skew_evd_info. */
-#define SKEW_EVD_K_PANEL 0   /* panel Householder QR (full-to-band) */
+#define SKEW_EVD_K_PANEL 0   /* panel Householder QR (full-to-band); the whole one-stage reduction */
 #define SKEW_EVD_K_SYMM 1    /* Y = A V T and W = Y - V X / 2 (full-to-band) */
 #define SKEW_EVD_K_SYR2K 2   /* A += V W^T - W V^T (full-to-band) */
 #define SKEW_EVD_K_CHASE 3   /* bulge chasing */
@@ -179,14 +205,14 @@ int skew_evd(int n, const double *A, int lda, int nev,
              double *lambda, double *Z_re, double *Z_im);
 
 /* Batched form: count independent problems (host arrays of per-problem sizes
- * and device pointers), each solved as by skew_evd_ex with ldz = n[i].
+ * and device pointers), each solved as by skew_evd_ex with ldz = n[i] (the
+ * two-stage FP64 route: opts->precision and opts->reduction other than the
+ * defaults return -10).
  * Problems up to n = 4096 are solved together: their stages run side by side
  * on 16 streams of the handle (HIP maps streams onto GPU_MAX_HW_QUEUES
  * hardware queues per process, 4 unless the environment sets more; 16 lets
  * them all run at once) and one bulge-chase launch serves all bands.
- * Only opts->precision = SKEW_EVD_PREC_FP64 is accepted (any other value
- * returns -10): the precision form is solved one problem at a time with
- * skew_evd_ex.
+ * The precision form is solved one problem at a time with skew_evd_ex.
  * status[i] (host) receives each problem's status; the return value is the
  * first non-zero status (or a negative argument error: -2 count, -3 n,
  * -4 A, -5 lda, -6 nev, -7 lambda, -8 Z_re, -9 Z_im, -12 status).  With

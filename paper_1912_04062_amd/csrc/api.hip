@@ -8,7 +8,6 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
-#include <thread>
 #include <vector>
 
 #include "../../include/skew_evd.h"
@@ -41,6 +40,8 @@ struct Plan {
     int npanels = 0, ngroups = 0, nsig = 0;
     int orth_window = 0;
     bool hh_panels = false;   // every panel by the Householder kernel (no Cholesky QR)
+    bool onestage = false;    // one-stage reduction to tridiagonal form (no band, no chase)
+    bool herm = false;        // the complex Hermitian route on iA (one stage, complex reflectors)
 };
 
 }  // namespace
@@ -96,16 +97,19 @@ namespace {
 // Workspace layout.  Offsets are 256-byte aligned.
 struct Layout {
     size_t W, Vall, Tall, tauall, Ypart, Y0, Wd, Gp, Tx, part, ab, goff, V2, tau2, T2, V2t, alpha, a2, stats,
-        lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, pshift, Qd, Z, cq, cqGp, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
+        lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, pshift, Qd, Z, Wos, oss, Wim, Vim, Tim, tauc, Wosi, dgl, Wp2, cq, cqGp, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
         rstat, Tm, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // offset (elements) of panel j's V_j in Vall: sum over i < j of (n - (i+1) b) b
+// (two-stage), of (n - i b - 1) b (one-stage: panel i's reflectors start at row
+// i b + 1)
 size_t voff(const Plan &p, int j)
 {
     const size_t n = p.n, b = p.b, jj = j;
+    if (p.onestage) return b * (jj * (n - 1) - b * jj * (jj - 1) / 2);
     return b * (jj * n - b * jj * (jj + 1) / 2);
 }
 
@@ -133,7 +137,7 @@ Layout plan_layout(const Plan &p)
     };
     L.W = take(es * n * n);
     size_t vtot = 0;
-    for (int j = 0; j < p.npanels; ++j) vtot += (n - (size_t)(j + 1) * b) * b;
+    for (int j = 0; j < p.npanels; ++j) vtot += (p.onestage ? n - (size_t)j * b - 1 : n - (size_t)(j + 1) * b) * b;
     L.Vall = take(es * vtot);
     L.Tall = take(sizeof(double) * (size_t)std::max(p.npanels, 1) * b * b);
     L.Tm = take(sizeof(double) * (size_t)(p.npanels / 2 + 1) * 4 * b * b);
@@ -178,6 +182,22 @@ Layout plan_layout(const Plan &p)
     L.Rinv = take(sizeof(double) * ORTH_NB * ORTH_NB);
     L.Tmp = take(sizeof(double) * n * ORTH_NB);
     L.ctl = take(sizeof(unsigned) * (64 + n));
+    L.Wos = p.onestage ? take(sizeof(double) * n * 64) : 0;
+    L.oss = p.onestage ? take(sizeof(double) * (p.herm ? skew::herm_scratch_doubles((int)n)
+                                                         : skew::onestage_scratch_doubles((int)n)))
+                       : 0;
+    L.Wim = L.Vim = L.Tim = L.tauc = L.Wosi = L.dgl = L.Wp2 = 0;
+    if (p.herm) {
+        // the imaginary planes of H, V, T and W, complex tau, the diagonal,
+        // and the second set of GEMM partials of the back-transformation
+        L.Wim = take(sizeof(double) * n * n);
+        L.Vim = take(sizeof(double) * vtot);
+        L.Tim = take(sizeof(double) * (size_t)std::max(p.npanels, 1) * b * b);
+        L.tauc = take(sizeof(double) * (size_t)std::max(p.npanels, 1) * 2 * b);
+        L.Wosi = take(sizeof(double) * n * 64);
+        L.dgl = take(sizeof(double) * n);
+        L.Wp2 = take(sizeof(double) * tn_parts_max() * b * 2 * nev);
+    }
     if (p.prec) {
         const size_t ncx = n;   // 2 nev columns (2 nev - 1 for odd n); nev = ceil(n/2) for the full half
         const size_t nc = std::max((size_t)2 * nev, ncx);
@@ -214,9 +234,21 @@ int auto_band(int n)
 // them per size class only where they win.)
 constexpr int HH_PANEL_NMAX = 0;
 
-Plan make_plan(int n, int nev, int b, int prec, int panel = SKEW_EVD_PANEL_AUTO)
+Plan make_plan(int n, int nev, int b, int prec, int panel = SKEW_EVD_PANEL_AUTO, bool onestage = false,
+               bool herm = false)
 {
     Plan p;
+    if (onestage || herm) {
+        // panels of 64 columns over columns 0 .. n-2 (the last one with a sub-diagonal entry)
+        p.onestage = true;
+        p.herm = herm;
+        p.n = n;
+        p.nev = nev;
+        p.b = p.nb2 = 64;
+        p.npanels = n >= 2 ? (n - 1 + 63) / 64 : 0;
+        p.orth_window = nev <= 2048 ? nev : 1024;
+        return p;
+    }
     p.hh_panels = panel == SKEW_EVD_PANEL_HOUSEHOLDER || (panel == SKEW_EVD_PANEL_AUTO && n <= HH_PANEL_NMAX);
     p.n = n;
     p.nev = nev;
@@ -344,6 +376,32 @@ void kt_counts(const struct Plan &p, skew_evd_info *info)
     k[SKEW_EVD_K_BT1].bytes = es * 3.0 * sm * 2.0 * nev;
     k[SKEW_EVD_K_BT1].bound = SKEW_EVD_BOUND_MFMA;
     k[SKEW_EVD_K_REFINE].bound = SKEW_EVD_BOUND_MFMA;
+    if (p.onestage) {
+        // the panel loop is the whole reduction: per column, the skew matrix-
+        // vector product streams the stored trailing triangle (m_c^2 / 2
+        // words, 2 m_c^2 flops); per panel, the rank-2b update reads and
+        // writes it (M^2 words, 2 M^2 b flops)
+        double sc = 0.0, sp = 0.0, sb = 0.0;
+        for (int c = 0; c + 1 < p.n; ++c) {
+            const double m = n - c - 1.0;
+            sc += m * m;
+        }
+        for (int j = 0; j < p.npanels; ++j) {
+            const double M = n - (double)(j + 1) * b;
+            if (M > 1.0) sp += M * M;
+            sb += n - (double)j * b - 1.0;
+        }
+        for (int q = SKEW_EVD_K_SYMM; q <= SKEW_EVD_K_BT2; ++q)
+            if (q != SKEW_EVD_K_TRIDIAG) k[q].flops = k[q].bytes = 0.0;
+        // complex Hermitian route: entries of 16 bytes, 8 flops per complex
+        // multiply-add, twice the real back-transformation's products
+        const double cw = p.herm ? 2.0 : 1.0, cf = p.herm ? 4.0 : 1.0;
+        k[SKEW_EVD_K_PANEL].flops = cf * (2.0 * sc + 2.0 * sp * b);
+        k[SKEW_EVD_K_PANEL].bytes = cw * 8.0 * (sc / 2.0 + sp);
+        k[SKEW_EVD_K_PANEL].bound = SKEW_EVD_BOUND_HBM;
+        k[SKEW_EVD_K_BT1].flops = cw * 8.0 * b * nev * sb;
+        k[SKEW_EVD_K_BT1].bytes = cw * 8.0 * 3.0 * sb * 2.0 * nev;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -565,6 +623,126 @@ int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, 
 
 int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L);
 
+// One-stage reduction (Section 2.3.1): the strict lower triangle into W, then
+// the panels of 64 columns; alpha, the panels' V and T (kept for the
+// back-transformation) and tau.  The chase's stage events mark no time.
+int stage_onestage(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, int lda)
+{
+    hipStream_t st = h->stream;
+    const int n = p.n;
+    double *W = ptr<double>(h, L.W);
+    skew::launch_ingest<double>(A, lda, n, W, n, ptr<unsigned>(h, L.ctl) + CTL_FLAGS, st);
+    HCHK(hipGetLastError());
+    HCHK(ev_record(h, 1));
+    HCHK(kt_begin(h, SKEW_EVD_K_PANEL));
+    for (int j = 0; j < p.npanels; ++j) {
+        const int c0 = 64 * j, nb = std::min(64, n - 1 - c0), ldv = n - c0 - 1;
+        double *Vp = ptr<double>(h, L.Vall) + voff(p, j);
+        double *Tp = ptr<double>(h, L.Tall) + (size_t)j * 64 * 64;
+        if (nb < 64) {                      // the last panel: unused reflectors are zero
+            skew::launch_fill32(Vp + (size_t)nb * ldv, 0u, 2 * (size_t)(64 - nb) * ldv, st);
+            skew::launch_fill32(Tp, 0u, 2 * 64 * 64, st);
+        }
+        skew::launch_onestage_panel(W, n, n, c0, nb, Vp, ptr<double>(h, L.Wos), ldv,
+                                    ptr<double>(h, L.tauall) + (size_t)j * 64, Tp, ptr<double>(h, L.alpha),
+                                    ptr<double>(h, L.oss), st);
+        HCHK(hipGetLastError());
+    }
+    HCHK(kt_end(h, SKEW_EVD_K_PANEL));
+    HCHK(ev_record(h, 2));
+    HCHK(ev_record(h, 3));
+    return SKEW_EVD_OK;
+}
+
+// Its back-transformation: D, then Z <- (I - V_j T_j V_j^T) Z for the panels in
+// reverse (rows from 64 j + 1).
+int stage_bt_onestage(skew_evd_handle h, const Plan &p, const Layout &L)
+{
+    hipStream_t st = h->stream;
+    const int n = p.n, nev = p.nev;
+    double *Z = ptr<double>(h, L.Z);
+    skew::launch_dscale<double>(ptr<double>(h, L.Qd), n, n, nev, Z, n, st);
+    HCHK(ev_record(h, 5));
+    HCHK(kt_begin(h, SKEW_EVD_K_BT1));
+    for (int j = p.npanels - 1; j >= 0; --j) {
+        const int c0 = 64 * j, m = n - c0 - 1;
+        skew::launch_bt1_block<double>(Z, n, c0 + 1, m, 2 * nev, ptr<double>(h, L.Vall) + voff(p, j), 64, nullptr,
+                                       0, ptr<double>(h, L.Tall) + (size_t)j * 64 * 64, 64, ptr<double>(h, L.Wp),
+                                       ptr<double>(h, L.Wt2), st);
+        HCHK(hipGetLastError());
+    }
+    HCHK(kt_end(h, SKEW_EVD_K_BT1));
+    HCHK(ev_record(h, 6));
+    return SKEW_EVD_OK;
+}
+
+// The complex Hermitian route on H = iA: the lower triangle of H as two
+// planes (real part 0, imaginary part the strict lower triangle of A), then
+// the panels of 64 columns; the real tridiagonal matrix (diagonal dgl,
+// off-diagonal alpha), the panels' complex V and T kept for the
+// back-transformation.
+int stage_herm(skew_evd_handle h, const Plan &p, const Layout &L, const double *A, int lda)
+{
+    hipStream_t st = h->stream;
+    const int n = p.n;
+    double *Hr = ptr<double>(h, L.W), *Hi = ptr<double>(h, L.Wim);
+    skew::launch_fill32(Hr, 0u, 2 * (size_t)n * n, st);
+    skew::launch_ingest<double>(A, lda, n, Hi, n, ptr<unsigned>(h, L.ctl) + CTL_FLAGS, st);
+    HCHK(hipGetLastError());
+    HCHK(ev_record(h, 1));
+    HCHK(kt_begin(h, SKEW_EVD_K_PANEL));
+    double *d = ptr<double>(h, L.dgl);
+    for (int j = 0; j < p.npanels; ++j) {
+        const int c0 = 64 * j, nb = std::min(64, n - 1 - c0), ldv = n - c0 - 1;
+        double *Vr = ptr<double>(h, L.Vall) + voff(p, j), *Vi = ptr<double>(h, L.Vim) + voff(p, j);
+        double *Tr = ptr<double>(h, L.Tall) + (size_t)j * 64 * 64, *Ti = ptr<double>(h, L.Tim) + (size_t)j * 64 * 64;
+        if (nb < 64) {                      // the last panel: unused reflectors are zero
+            skew::launch_fill32(Vr + (size_t)nb * ldv, 0u, 2 * (size_t)(64 - nb) * ldv, st);
+            skew::launch_fill32(Vi + (size_t)nb * ldv, 0u, 2 * (size_t)(64 - nb) * ldv, st);
+            skew::launch_fill32(Tr, 0u, 2 * 64 * 64, st);
+            skew::launch_fill32(Ti, 0u, 2 * 64 * 64, st);
+        }
+        skew::launch_herm_panel(Hr, Hi, n, n, c0, nb, Vr, Vi, ptr<double>(h, L.Wos), ptr<double>(h, L.Wosi), ldv,
+                                ptr<double>(h, L.tauc) + (size_t)j * 128, Tr, Ti, d, ptr<double>(h, L.alpha),
+                                ptr<double>(h, L.oss), st);
+        HCHK(hipGetLastError());
+    }
+    // the last diagonal entry, after the last panel's trailing update
+    if (n >= 1)
+        HCHK(hipMemcpyAsync(d + (n - 1), Hr + (size_t)(n - 1) * n + (n - 1), sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    HCHK(kt_end(h, SKEW_EVD_K_PANEL));
+    HCHK(ev_record(h, 2));
+    HCHK(ev_record(h, 3));
+    return SKEW_EVD_OK;
+}
+
+// Its back-transformation: Z = [S, 0] (S the tridiagonal eigenvectors), then
+// Z <- (I - V_j T_j V_j^H) Z for the panels in reverse (rows from 64 j + 1),
+// then z = conj(x): the imaginary half negated.
+int stage_bt_herm(skew_evd_handle h, const Plan &p, const Layout &L)
+{
+    hipStream_t st = h->stream;
+    const int n = p.n, nev = p.nev;
+    double *Z = ptr<double>(h, L.Z);
+    skew::launch_copy_cols<double>(ptr<double>(h, L.Qd), n, Z, n, n, nev, st);
+    skew::launch_fill32(Z + (size_t)nev * n, 0u, 2 * (size_t)nev * n, st);
+    HCHK(ev_record(h, 5));
+    HCHK(kt_begin(h, SKEW_EVD_K_BT1));
+    for (int j = p.npanels - 1; j >= 0; --j) {
+        const int c0 = 64 * j, m = n - c0 - 1;
+        skew::launch_herm_bt(Z, n, c0 + 1, m, nev, ptr<double>(h, L.Vall) + voff(p, j),
+                             ptr<double>(h, L.Vim) + voff(p, j), ptr<double>(h, L.Tall) + (size_t)j * 64 * 64,
+                             ptr<double>(h, L.Tim) + (size_t)j * 64 * 64, ptr<double>(h, L.Wp),
+                             ptr<double>(h, L.Wp2), ptr<double>(h, L.Wt2), st);
+        HCHK(hipGetLastError());
+    }
+    skew::launch_negate(Z + (size_t)nev * n, (size_t)nev * n, st);
+    HCHK(kt_end(h, SKEW_EVD_K_BT1));
+    HCHK(ev_record(h, 6));
+    return SKEW_EVD_OK;
+}
+
 // Inverse iteration: a vector whose residual exceeds this multiple of ||T||
 // is reported as not converged.
 constexpr double INVIT_CTOL = 1e-12;
@@ -573,12 +751,13 @@ constexpr double INVIT_CTOL = 1e-12;
 // once the bisection (which fills the device) is queued, so that they run
 // beside the inverse iteration.
 int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const double *alpha, int nev, double *lam,
-                  double *Q, int ldq, bool early_t = false)
+                  double *Q, int ldq, bool early_t = false, const double *diag = nullptr)
 {
     hipStream_t st = h->stream;
     const int n = p.n;
     HCHK(kt_begin(h, SKEW_EVD_K_TRIDIAG));
-    skew::launch_tridiag_eigvals(alpha, n, n / 2, nev, ptr<double>(h, L.a2), ptr<double>(h, L.stats), lam, st);
+    skew::launch_tridiag_eigvals(alpha, n, n / 2, nev, ptr<double>(h, L.a2), ptr<double>(h, L.stats), lam, st,
+                                 diag);
     int rc = fetch_windows(h, p, L, lam, nev);
     if (rc) return rc;
     if (early_t) {
@@ -589,7 +768,7 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
     skew::launch_tridiag_eigvecs(alpha, n, nev, lam, ptr<double>(h, L.stats), ptr<double>(h, L.U0),
                                  ptr<double>(h, L.U1), ptr<double>(h, L.U2), ptr<double>(h, L.Lm),
                                  ptr<unsigned char>(h, L.Sw), ptr<double>(h, L.Yiv), ptr<double>(h, L.ivfac), Q,
-                                 ldq, ctol, ptr<unsigned>(h, L.ctl) + CTL_ERR, st);
+                                 ldq, ctol, ptr<unsigned>(h, L.ctl) + CTL_ERR, st, diag);
     HCHK(hipGetLastError());
     rc = plan_windows(h, p, nev);
     if (rc) return rc;
@@ -604,7 +783,7 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
         skew::launch_tridiag_polish(alpha, n, m, lam + lo, ptr<double>(h, L.pshift), ptr<double>(h, L.stats),
                                     ptr<double>(h, L.U0), ptr<double>(h, L.U1), ptr<double>(h, L.U2),
                                     ptr<double>(h, L.Lm), ptr<unsigned char>(h, L.Sw), ptr<double>(h, L.Yiv),
-                                    ptr<double>(h, L.ivfac), Q + (size_t)lo * ldq, ldq, st);
+                                    ptr<double>(h, L.ivfac), Q + (size_t)lo * ldq, ldq, st, diag);
         HCHK(hipGetLastError());
         rc = orthogonalize(h, p, L, Q, ldq, n, nev, (lo / ORTH_NB) * ORTH_NB);
         if (rc) return rc;
@@ -801,6 +980,11 @@ int validate_opts(const skew_evd_opts *o)
     if (o->debug & ~(SKEW_EVD_DEBUG_NAN_WS | SKEW_EVD_DEBUG_ZERO_WS | SKEW_EVD_DEBUG_INVIT_NOCONV)) return 1;
     if (o->all_pairs != 0 && o->all_pairs != 1) return 1;
     if (o->panel_method < SKEW_EVD_PANEL_AUTO || o->panel_method > SKEW_EVD_PANEL_HOUSEHOLDER) return 1;
+    if (o->reduction != SKEW_EVD_REDUCE_TWO_STAGE && o->reduction != SKEW_EVD_REDUCE_ONE_STAGE &&
+        o->reduction != SKEW_EVD_REDUCE_COMPLEX_HERMITIAN)
+        return 1;
+    // the one-stage routes are FP64 with their own panel width
+    if (o->reduction != SKEW_EVD_REDUCE_TWO_STAGE && (o->precision != SKEW_EVD_PREC_FP64 || o->band != 0)) return 1;
     return 0;
 }
 
@@ -896,7 +1080,8 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     // the refinement works on the whole invariant half: the precision form
     // always computes ceil(n/2) pairs and returns the first nev
     if (prec) nev = (n + 1) / 2;
-    Plan p = make_plan(n, nev, o.band, prec, o.panel_method);
+    Plan p = make_plan(n, nev, o.band, prec, o.panel_method, o.reduction == SKEW_EVD_REDUCE_ONE_STAGE,
+                       o.reduction == SKEW_EVD_REDUCE_COMPLEX_HERMITIAN);
     Layout L = plan_layout(p);
     int rc = ensure_ws(h, L.total, o.workspace_limit);
     if (rc) return rc;
@@ -912,18 +1097,25 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     skew::launch_fill32(ptr<unsigned>(h, L.ctl), 0u, 64, st);
     HCHK(ev_record(h, 0));
     rec[0] = true;
-    rc = prec ? stage_band<float>(h, p, L, A, lda, 1) : stage_band<double>(h, p, L, A, lda, 1);
+    if (p.herm) {
+        rc = stage_herm(h, p, L, A, lda);
+    } else if (p.onestage) {
+        rc = stage_onestage(h, p, L, A, lda);
+    } else {
+        rc = prec ? stage_band<float>(h, p, L, A, lda, 1) : stage_band<double>(h, p, L, A, lda, 1);
+        if (rc) return rc;
+        rc = stage_chase(h, p, L);
+    }
     if (rc) return rc;
-    rec[1] = rec[2] = true;
-    rc = stage_chase(h, p, L);
-    if (rc) return rc;
-    rec[3] = true;
+    rec[1] = rec[2] = rec[3] = true;
     const bool early_t = n >= EARLY_TFAC_MIN_N && p.ngroups > 0;
     rc = stage_tridiag(h, p, L, ptr<double>(h, L.alpha), nev, ptr<double>(h, L.lam), ptr<double>(h, L.Qd), n,
-                       early_t);
+                       early_t, p.herm ? ptr<double>(h, L.dgl) : nullptr);
     if (rc) return rc;
     rec[4] = true;
-    rc = prec ? stage_backtransform<float>(h, p, L, early_t) : stage_backtransform<double>(h, p, L, early_t);
+    if (p.herm) rc = stage_bt_herm(h, p, L);
+    else if (p.onestage) rc = stage_bt_onestage(h, p, L);
+    else rc = prec ? stage_backtransform<float>(h, p, L, early_t) : stage_backtransform<double>(h, p, L, early_t);
     if (rc) return rc;
     rec[5] = rec[6] = true;
     int rsweeps = 0, refine_rc = SKEW_EVD_OK;
@@ -1446,19 +1638,22 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
     std::vector<skew_evd_handle_s *> views(cnt);
     for (int s2 = 0; s2 < S; ++s2)
         for (int k : part[s2]) views[k] = make_view(h, it[k], h->sub_streams[s2]);
+    // One host thread enqueues everything, taking the streams in turn (problem
+    // r of every stream, then problem r + 1, ...): the device starts on the
+    // first problems while the rest are enqueued.  (With one enqueueing thread
+    // per stream, the launches of several threads met inside the runtime, and
+    // a profiler's interception of them crashed.)
     std::vector<int> src(S, SKEW_EVD_OK);
+    size_t rounds = 0;
+    for (int s2 = 0; s2 < S; ++s2) rounds = std::max(rounds, part[s2].size());
     auto run_parts = [&](bool first) {
-        std::vector<std::thread> workers;
-        for (int s2 = 0; s2 < S; ++s2)
-            workers.emplace_back([&, s2]() {
-                for (int k : part[s2]) {
-                    if (src[s2]) return;
-                    const int i = it[k].idx;
-                    src[s2] = first ? batch_part_a(views[k], it[k], A[i], lda[i])
-                                    : batch_part_c(views[k], it[k], lambda[i], Z_re[i], Z_im[i], dstat + 2 * k);
-                }
-            });
-        for (auto &w : workers) w.join();
+        for (size_t r = 0; r < rounds; ++r)
+            for (int s2 = 0; s2 < S; ++s2) {
+                if (r >= part[s2].size() || src[s2]) continue;
+                const int k = part[s2][r], i = it[k].idx;
+                src[s2] = first ? batch_part_a(views[k], it[k], A[i], lda[i])
+                                : batch_part_c(views[k], it[k], lambda[i], Z_re[i], Z_im[i], dstat + 2 * k);
+            }
     };
     rc = fork_streams(h, S);
     if (!rc) {
@@ -1509,8 +1704,9 @@ int skew_evd_batched(skew_evd_handle h, int count, const int *n, const double *c
         return -12;
     }
     if (validate_opts(opts)) return -10;
-    // the precision form is not available in the batched form (see the header)
-    if (opts && opts->precision != SKEW_EVD_PREC_FP64) return -10;
+    // the precision form and the one-stage route are not available in the
+    // batched form (see the header)
+    if (opts && (opts->precision != SKEW_EVD_PREC_FP64 || opts->reduction != SKEW_EVD_REDUCE_TWO_STAGE)) return -10;
     for (int i = 0; i < count; ++i) {
         if (n[i] < 0) return -3;
         if (n[i] > 0 && !A[i]) return -4;

@@ -340,19 +340,10 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_wform(const T *__restrict__ Y
 }
 
 // Lower tiles (I >= J) of the trailing block: A += V W^T - W V^T.
-__device__ __forceinline__ void tri_index(int t, int &I, int &J)
-{
-    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    I = i;
-    J = t - i * (i + 1) / 2;
-}
-
 template <typename T, int TT>
 __global__ __launch_bounds__(256) GEMM_OCC2 void k_skew_syr2k(T *__restrict__ W, int ldw, int r0, int m,
                                                     const T *__restrict__ Vd, const T *__restrict__ Wd,
-                                                    int B)
+                                                    int B, int ldv)
 {
     extern __shared__ char smraw[];
     T *smem = (T *)smraw;
@@ -363,12 +354,12 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_skew_syr2k(T *__restrict__ W,
     // around the loads); k < 2B always
     auto fa = [=](int i, int k) -> T {
         const bool lo = k < B;
-        const T x = (lo ? Vd : Wd)[(size_t)(lo ? k : k - B) * m + min(i, m - 1)];
+        const T x = (lo ? Vd : Wd)[(size_t)(lo ? k : k - B) * ldv + min(i, m - 1)];
         return x * T(i < m ? 1 : 0);
     };
     auto fb = [=](int j, int k) -> T {
         const bool lo = k < B;
-        const T x = (lo ? Wd : Vd)[(size_t)(lo ? k : k - B) * m + min(j, m - 1)];
+        const T x = (lo ? Wd : Vd)[(size_t)(lo ? k : k - B) * ldv + min(j, m - 1)];
         return x * T(j < m ? (lo ? 1 : -1) : 0);
     };
     gemm::Acc<T, TT, TT> acc;
@@ -744,13 +735,19 @@ void launch_stage1_w(T *W, int ldw, int r0, int m, int B, const T *Vd, const dou
 }
 
 template <typename T>
-void launch_stage1_syr2k(T *W, int ldw, int r0, int m, int B, const T *Vd, const T *Wd, hipStream_t st)
+void launch_syr2k_ld(T *W, int ldw, int r0, int m, int B, const T *Vd, const T *Wd, int ldv, hipStream_t st)
 {
     const int TT = 64;
     unsigned nt = cdiv(m, TT);
     unsigned ntiles = nt * (nt + 1) / 2;
     hipLaunchKernelGGL((k_skew_syr2k<T, 64>), dim3(ntiles), dim3(256), (gemm::smem_bytes<T, 64, 64>()), st,
-                       W, ldw, r0, m, Vd, (const T *)Wd, B);
+                       W, ldw, r0, m, Vd, (const T *)Wd, B, ldv);
+}
+
+template <typename T>
+void launch_stage1_syr2k(T *W, int ldw, int r0, int m, int B, const T *Vd, const T *Wd, hipStream_t st)
+{
+    launch_syr2k_ld<T>(W, ldw, r0, m, B, Vd, Wd, m, st);
 }
 
 template <typename T>
@@ -795,6 +792,8 @@ template void launch_stage1_w<float>(float *, int, int, int, int, const float *,
                                      float *, float *, double *, float *, hipStream_t);
 template void launch_stage1_syr2k<double>(double *, int, int, int, int, const double *, const double *,
                                           hipStream_t);
+template void launch_syr2k_ld<double>(double *, int, int, int, int, const double *, const double *, int,
+                                      hipStream_t);
 template void launch_stage1_syr2k<float>(float *, int, int, int, int, const float *, const float *,
                                          hipStream_t);
 template void launch_band_extract<double>(const double *, int, int, int, double *, int, hipStream_t);

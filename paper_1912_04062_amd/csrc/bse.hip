@@ -105,14 +105,6 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_panel_solve(double *__restric
     });
 }
 
-__device__ __forceinline__ void tri_index(int t, int &I, int &J)
-{
-    I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    while (I * (I + 1) / 2 > t) --I;
-    J = t - I * (I + 1) / 2;
-}
-
 // Step 2, trailing update: lower tiles (I >= J) of M[r0:, r0:] -= P P^T with
 // P = M[r0:r0+mr, j0:j0+nb] (the panel just solved).
 template <int TT>

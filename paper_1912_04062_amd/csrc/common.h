@@ -182,6 +182,16 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Tile t of the lower triangle of a tile grid, row by row: (I, J), J <= I.
+__device__ __forceinline__ void tri_index(int t, int &I, int &J)
+{
+    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
 // Wavefront sum (64 lanes) via cross-lane shuffles.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)

@@ -34,6 +34,9 @@ void launch_stage1_w(T *W, int ldw, int r0, int m, int B, const T *Vd, const dou
                      T *Y0, T *Wd, double *Gp, T *Tx, hipStream_t st);
 template <typename T>
 void launch_stage1_syr2k(T *W, int ldw, int r0, int m, int B, const T *Vd, const T *Wd, hipStream_t st);
+// the same with V and W of leading dimension ldv (>= m)
+template <typename T>
+void launch_syr2k_ld(T *W, int ldw, int r0, int m, int B, const T *Vd, const T *Wd, int ldv, hipStream_t st);
 template <typename T>
 void launch_band_extract(const T *W, int ldw, int n, int b, double *ab, int ldab, hipStream_t st);
 
@@ -58,14 +61,17 @@ int chase_max_workgroups();
 void launch_goff(int n, int b, int nb2, int *goff, hipStream_t st);
 
 // tridiag.hip
+// diag: the diagonal of a general symmetric tridiagonal matrix (n entries),
+// or null for the zero diagonal of Lemma 1
 void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, double *a2, double *stats,
-                            double *w, hipStream_t st);
+                            double *w, hipStream_t st, const double *diag = nullptr);
 void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
                             double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
-                            double *fac, double *Q, int ldq, double ctol, unsigned *err, hipStream_t st);
+                            double *fac, double *Q, int ldq, double ctol, unsigned *err, hipStream_t st,
+                            const double *diag = nullptr);
 void launch_tridiag_polish(const double *alpha, int n, int m, const double *w, const double *shifts,
                            const double *stats, double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw,
-                           double *Y, double *fac, double *Q, int ldq, hipStream_t st);
+                           double *Y, double *fac, double *Q, int ldq, hipStream_t st, const double *diag = nullptr);
 // sets *flag when two consecutive values of w[0..m) are closer than tol * stats[0]
 void launch_degenerate_check(const double *w, int m, const double *stats, double tol, unsigned *flag,
                              hipStream_t st);
@@ -105,6 +111,20 @@ template <typename T>
 void launch_bt1_block(T *Z, int ldz, int r0, int m, int ncols, const T *V1, int b1, const T *V2, int m2,
                       const double *Tm, int KK, double *Wp, T *W2, hipStream_t st);
 void launch_merge_t(const double *T1, const double *T2, const double *Gp, int S, int b, double *Tm, hipStream_t st);
+
+// onestage.hip (one-stage tridiagonalization)
+size_t onestage_scratch_doubles(int n);
+void launch_onestage_panel(double *A, int lda, int n, int c0, int nb, double *V, double *W, int ldv, double *tau,
+                           double *T, double *alpha, double *scratch, hipStream_t st);
+
+// hermitian.hip (the complex Hermitian route on iA)
+size_t herm_scratch_doubles(int n);
+void launch_herm_panel(double *Hr, double *Hi, int lda, int n, int c0, int nb, double *Vr, double *Vi, double *Wr,
+                       double *Wi, int ldv, double *tau, double *Tr, double *Ti, double *d, double *e,
+                       double *scratch, hipStream_t st);
+void launch_herm_bt(double *Z, int ldz, int r0, int m, int nev, const double *Vr, const double *Vi, const double *Tr,
+                    const double *Ti, double *P1, double *P2, double *B, hipStream_t st);
+void launch_negate(double *X, size_t count, hipStream_t st);
 
 // bse.hip (the Bethe-Salpeter route)
 void launch_bse_build_m(const double *Ar, const double *Ai, int lda, const double *Br, const double *Bi, int ldb,

@@ -1,6 +1,9 @@
 // Symmetric tridiagonal eigensolver for T = tridiag(alpha, 0, alpha)
 // (Algorithm 1, step 2; Lemma 1 turns the skew tridiagonal into this matrix,
-// whose off-diagonal is the super-diagonal alpha of the skew one).
+// whose off-diagonal is the super-diagonal alpha of the skew one).  With a
+// diagonal given, the same kernels solve tridiag(alpha, diag, alpha) (the
+// complex Hermitian route's real tridiagonal matrix): the Sturm counts and
+// the factorizations take d_i - x, and each vector is normalised as a whole.
 //
 //   k_bisect   eigenvalues by Sturm-sequence multisection: 16 lanes evaluate
 //              the inertia count at 16 interior points of the current
@@ -29,7 +32,7 @@ constexpr int BIS_NS = 16;       // shifts per eigenvalue
 constexpr int BIS_CH = 2048;     // alpha^2 chunk staged in LDS
 
 __global__ void k_alpha2(const double *__restrict__ alpha, int n, double *__restrict__ a2,
-                         double *__restrict__ stats)
+                         double *__restrict__ stats, const double *__restrict__ diag)
 {
     // a2[i] = alpha[i]^2 (i < n-1); stats[0] = ||T||_inf, stats[1] = max alpha^2
     __shared__ double mx[256], mg[256];
@@ -38,10 +41,15 @@ __global__ void k_alpha2(const double *__restrict__ alpha, int n, double *__rest
         double a = alpha[i];
         a2[i] = a * a;
         lm = fmax(lm, a * a);
-        double r = fabs(a) + ((i + 1 < n - 1) ? fabs(alpha[i + 1]) : 0.0);
-        lg = fmax(lg, r);
-        if (i == 0) lg = fmax(lg, fabs(a));
+        if (!diag) {
+            double r = fabs(a) + ((i + 1 < n - 1) ? fabs(alpha[i + 1]) : 0.0);
+            lg = fmax(lg, r);
+            if (i == 0) lg = fmax(lg, fabs(a));
+        }
     }
+    if (diag)       // row i: |d_i| + |alpha_{i-1}| + |alpha_i|
+        for (int i = threadIdx.x; i < n; i += 256)
+            lg = fmax(lg, fabs(diag[i]) + ((i > 0) ? fabs(alpha[i - 1]) : 0.0) + ((i < n - 1) ? fabs(alpha[i]) : 0.0));
     mx[threadIdx.x] = lm;
     mg[threadIdx.x] = lg;
     __syncthreads();
@@ -73,9 +81,9 @@ __device__ __forceinline__ double recip(double d)
 // 256 threads = 16 eigenvalues x 16 shifts.  Eigenvalue index first + e.
 __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, int n, int first, int count,
                                                 const double *__restrict__ stats, int rounds,
-                                                double *__restrict__ w)
+                                                double *__restrict__ w, const double *__restrict__ diag)
 {
-    __shared__ double sa[BIS_CH];
+    __shared__ double sa[BIS_CH], sd[BIS_CH];
     const int q = threadIdx.x & (BIS_NS - 1);
     const int e = blockIdx.x * (256 / BIS_NS) + threadIdx.x / BIS_NS;
     const bool active = e < count;
@@ -88,18 +96,29 @@ __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, i
     for (int r = 0; r < rounds; ++r) {
         const double h = (hi - lo) / (BIS_NS + 1);
         const double xq = lo + (q + 1) * h;
-        double d = -xq;
+        double d = diag ? diag[0] - xq : -xq;
         if (fabs(d) < pivmin) d = -pivmin;
         int cnt = (d < 0.0) ? 1 : 0;
         for (int c0 = 0; c0 < n - 1; c0 += BIS_CH) {
             const int len = min(BIS_CH, n - 1 - c0);
             __syncthreads();
-            for (int i = threadIdx.x; i < len; i += 256) sa[i] = a2[c0 + i];
+            for (int i = threadIdx.x; i < len; i += 256) {
+                sa[i] = a2[c0 + i];
+                if (diag) sd[i] = diag[c0 + i + 1];
+            }
             __syncthreads();
-            for (int i = 0; i < len; ++i) {
-                d = -xq - sa[i] * recip(d);
-                if (fabs(d) < pivmin) d = -pivmin;
-                cnt += (d < 0.0) ? 1 : 0;
+            if (diag) {
+                for (int i = 0; i < len; ++i) {
+                    d = (sd[i] - xq) - sa[i] * recip(d);
+                    if (fabs(d) < pivmin) d = -pivmin;
+                    cnt += (d < 0.0) ? 1 : 0;
+                }
+            } else {
+                for (int i = 0; i < len; ++i) {
+                    d = -xq - sa[i] * recip(d);
+                    if (fabs(d) < pivmin) d = -pivmin;
+                    cnt += (d < 0.0) ? 1 : 0;
+                }
             }
         }
         // lanes with count <= idx have lambda_idx >= x_q
@@ -112,12 +131,15 @@ __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, i
         hi = nhi;
     }
     if (active && q == 0) {
-        // the requested indices are the upper half of a spectrum symmetric
-        // about 0, so lambda >= 0: a final bracket that still holds 0 (the
-        // zero matrix, or a split block of odd order) gives exactly 0, which
-        // is as close as its midpoint
-        double lam = (lo <= 0.0) ? 0.0 : 0.5 * (lo + hi);
-        if ((n & 1) && idx == n / 2) lam = 0.0;
+        // zero diagonal: the requested indices are the upper half of a
+        // spectrum symmetric about 0, so lambda >= 0: a final bracket that
+        // still holds 0 (the zero matrix, or a split block of odd order)
+        // gives exactly 0, which is as close as its midpoint
+        double lam = 0.5 * (lo + hi);
+        if (!diag) {
+            if (lo <= 0.0) lam = 0.0;
+            if ((n & 1) && idx == n / 2) lam = 0.0;
+        }
         w[e] = lam;
     }
 }
@@ -160,7 +182,7 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
                                               double *__restrict__ U2, double *__restrict__ Lm,
                                               unsigned char *__restrict__ Sw, double *__restrict__ Y,
                                               double *__restrict__ fac, double ctol, unsigned *err,
-                                              const double *__restrict__ shifts)
+                                              const double *__restrict__ shifts, const double *__restrict__ diag)
 {
     const int k = blockIdx.x * 64 + threadIdx.x;
     if (k >= nev) return;
@@ -181,19 +203,21 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
     auto clampu = [=](double u) { return (fabs(u) < tiny) ? ((u < 0.0) ? -tiny : tiny) : u; };
     // factor T - shift I with partial pivoting (rows i, i+1 at step i)
     {
-        double a = -shift, bb = (n > 1) ? alpha[0] : 0.0, cc = 0.0;
+        double a = diag ? diag[0] - shift : -shift, bb = (n > 1) ? alpha[0] : 0.0, cc = 0.0;
         for (int i0 = 0; i0 + 1 < n; i0 += IV_CH) {
-            double al[IV_CH + 1];
+            double al[IV_CH + 1], dl[IV_CH];
 #pragma unroll
             for (int j = 0; j <= IV_CH; ++j) {
                 const double x = alpha[min(i0 + j, n - 2)];
                 al[j] = (i0 + j < n - 1) ? x : 0.0;
             }
 #pragma unroll
+            for (int j = 0; j < IV_CH; ++j) dl[j] = diag ? diag[min(i0 + j + 1, n - 1)] : 0.0;
+#pragma unroll
             for (int j = 0; j < IV_CH; ++j) {
                 const int i = i0 + j;
                 if (i + 1 >= n) continue;           // predicated (no break: keeps the loop unrolled)
-                const double sub = al[j], dn = -shift, en = al[j + 1];
+                const double sub = al[j], dn = diag ? dl[j] - shift : -shift, en = al[j + 1];
                 // the pivot is clamped away from 0 (the factorization is
                 // that of T - shift I perturbed by at most tiny) and stored
                 // as its reciprocal
@@ -295,7 +319,7 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
     if (err && g > 0.0 && !(sqrt(se + so) * ctol * g >= 1.0)) atomicOr(err, ERR_INVIT);
     // final scaling factors
     double fe, fo;
-    if (lam > 0.0 && se > 0.0 && so > 0.0) {
+    if (!diag && lam > 0.0 && se > 0.0 && so > 0.0) {
         fe = sqrt(0.5 / se);
         fo = sqrt(0.5 / so);
     } else {
@@ -435,23 +459,24 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp,
 namespace skew {
 
 void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, double *a2, double *stats,
-                            double *w, hipStream_t st)
+                            double *w, hipStream_t st, const double *diag)
 {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_alpha2, dim3(1), dim3(256), 0, st, alpha, n, a2, stats);
+    hipLaunchKernelGGL(k_alpha2, dim3(1), dim3(256), 0, st, alpha, n, a2, stats, diag);
     const int rounds = 14;   // 17^14 > 2^57
     hipLaunchKernelGGL(k_bisect, dim3(cdiv(count, 256 / BIS_NS)), dim3(256), 0, st, (const double *)a2, n, first,
-                       count, (const double *)stats, rounds, w);
+                       count, (const double *)stats, rounds, w, diag);
 }
 
 void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
                             double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
-                            double *fac, double *Q, int ldq, double ctol, unsigned *err, hipStream_t st)
+                            double *fac, double *Q, int ldq, double ctol, unsigned *err, hipStream_t st,
+                            const double *diag)
 {
     if (nev <= 0) return;
     hipLaunchKernelGGL(k_invit, dim3(cdiv(nev, 64)), dim3(64), 0, st, alpha, n, nev, w, stats, 3, U0, U1, U2,
-                       Lm, Sw, Y, fac, ctol, err, (const double *)nullptr);
-    if (n & 1) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, alpha, n, nev, Y, fac);
+                       Lm, Sw, Y, fac, ctol, err, (const double *)nullptr, diag);
+    if ((n & 1) && !diag) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, alpha, n, nev, Y, fac);
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(nev, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Y, n,
                        nev, (const double *)fac, Q, ldq);
 }
@@ -462,13 +487,13 @@ void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w
 // launch_tridiag_eigvecs, used with m in place of nev.
 void launch_tridiag_polish(const double *alpha, int n, int m, const double *w, const double *shifts,
                            const double *stats, double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw,
-                           double *Y, double *fac, double *Q, int ldq, hipStream_t st)
+                           double *Y, double *fac, double *Q, int ldq, hipStream_t st, const double *diag)
 {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_transpose_in, dim3(cdiv(m, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Q, ldq, n,
                        m, Y);
     hipLaunchKernelGGL(k_invit, dim3(cdiv(m, 64)), dim3(64), 0, st, alpha, n, m, w, stats, 1, U0, U1, U2, Lm, Sw,
-                       Y, fac, 1e300, (unsigned *)nullptr, shifts);
+                       Y, fac, 1e300, (unsigned *)nullptr, shifts, diag);
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(m, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Y, n, m,
                        (const double *)fac, Q, ldq);
 }

@@ -32,6 +32,10 @@ DEBUG_NAN_WS = 1
 DEBUG_ZERO_WS = 2
 DEBUG_INVIT_NOCONV = 4
 _PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32_REFINE, "fp32_refine": PREC_FP32_REFINE}
+REDUCE_TWO_STAGE = 0
+REDUCE_ONE_STAGE = 1
+REDUCE_COMPLEX_HERMITIAN = 2
+_REDUCE = {"two": REDUCE_TWO_STAGE, "one": REDUCE_ONE_STAGE, "complex": REDUCE_COMPLEX_HERMITIAN}
 
 
 class Opts(ctypes.Structure):
@@ -40,7 +44,7 @@ class Opts(ctypes.Structure):
                 ("workspace_limit", ctypes.c_size_t), ("profile", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("no_fp64_fallback", ctypes.c_int),
                 ("debug", ctypes.c_int), ("all_pairs", ctypes.c_int), ("panel_method", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("reduction", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 class KStat(ctypes.Structure):
@@ -134,7 +138,7 @@ def status_string(status):
 
 def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=None,
                  workspace_limit=0, profile=0, autotune=0, no_fp64_fallback=0, debug=0, all_pairs=0,
-                 panel_method=0):
+                 panel_method=0, reduction=0):
     o = Opts()
     _load().skew_evd_default_opts(ctypes.byref(o))
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
@@ -150,6 +154,7 @@ def default_opts(precision="fp64", band=0, max_refine_sweeps=None, refine_tol=No
     o.debug = int(debug)
     o.all_pairs = int(all_pairs)
     o.panel_method = int(panel_method)
+    o.reduction = _REDUCE[reduction] if isinstance(reduction, str) else int(reduction)
     return o
 
 
@@ -255,7 +260,7 @@ class Handle:
             raise SkewEvdError(st, "skew_evd_autotune")
         return b.value, ms.value
 
-    def solve_batched(self, mats, precision="fp64", band=0, autotune=0, nevs=None):
+    def solve_batched(self, mats, precision="fp64", band=0, autotune=0, nevs=None, reduction=0):
         """Solve a list of skew matrices (each n_i x n_i float64 CUDA); returns
         a list of (lam, Zre, Zim), the per-problem status list and the call's
         status.  nevs: eigenpairs per problem (default ceil(n_i / 2))."""
@@ -277,7 +282,7 @@ class Handle:
         zr_a = PtrA(*[o[1].data_ptr() for o in outs])
         zi_a = PtrA(*[o[2].data_ptr() for o in outs])
         status = IntA()
-        o = default_opts(precision, band, autotune=autotune)
+        o = default_opts(precision, band, autotune=autotune, reduction=reduction)
         inf = Info()
         st = self._lib.skew_evd_batched(self._h, count, n_a, A_a, lda_a, nev_a, l_a, zr_a, zi_a,
                                         ctypes.byref(o), ctypes.byref(inf), status)

@@ -237,3 +237,88 @@ def test_panel_methods(h, n, pm):
     assert np.max(np.abs(lam - lref)) <= TOL_EIG * nA
     res, orth, _ = metrics(A, lam, Z, nA)
     assert res <= TOL_RES and orth <= TOL_ORTH
+
+
+def _route_vs_oracle(h, A, reduction, label):
+    import oracle
+    import torch
+    from paper_1912_04062_amd import skewevd
+    n = A.shape[0]
+    lam, zr, zi = h.solve(to_dev(A), opts=skewevd.default_opts(reduction=reduction))
+    torch.cuda.synchronize()
+    lam = lam.cpu().numpy()
+    Z = zr.cpu().numpy() + 1j * zi.cpu().numpy()
+    lref, _ = oracle.skew_evd(A)
+    nA = max(lref.max(), 1.0) if n > 1 else 1.0
+    err = np.max(np.abs(lam - lref)) / nA
+    if n > 1:
+        res, orth, _ = metrics(A, lam, Z, nA)
+        print(f"  {label}: eig err={err:.2e} res={res:.2e} orth={orth:.2e}", flush=True)
+        assert res <= TOL_RES and orth <= TOL_ORTH
+    assert err <= TOL_EIG
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 65, 130, 300, 1001, 2050, 4100])
+def test_one_stage_route(h, n):
+    """The one-stage reduction (Section 2.3.1) with its one-stage
+    back-transformation: eigenpairs within the FP64 tolerances of the oracle,
+    ragged last panels and n above the fixed Gram-Schmidt window included."""
+    print(f"one-stage n={n}", flush=True)
+    _route_vs_oracle(h, wl.random_skew(n, 1700 + n), 1, "one-stage")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 65, 130, 300, 1001, 2050])
+def test_complex_hermitian_route(h, n):
+    """The complex Hermitian route on iA (the comparison of the introduction
+    and Section 4.1): complex one-stage reduction, the real tridiagonal
+    matrix with its diagonal, complex back-transformation; eigenpairs within
+    the FP64 tolerances of the oracle in the skew solver's form."""
+    print(f"complex Hermitian n={n}", flush=True)
+    _route_vs_oracle(h, wl.random_skew(n, 1900 + n), 2, "complex")
+
+
+def test_complex_hermitian_route_prescribed(h):
+    """Known spectrum with close pairs (prescribed l_k) through the complex
+    route: every eigenvalue against l_k."""
+    import torch
+    from paper_1912_04062_amd import skewevd
+    n = 700
+    A, l, _ = wl.prescribed(n, 23)
+    lam, zr, zi = h.solve(to_dev(A), opts=skewevd.default_opts(reduction=2))
+    torch.cuda.synchronize()
+    exact = np.sort(l)
+    nA = exact.max()
+    err = np.max(np.abs(np.sort(lam.cpu().numpy()) - exact)) / nA
+    Z = zr.cpu().numpy() + 1j * zi.cpu().numpy()
+    res, orth, _ = metrics(A, lam.cpu().numpy(), Z, nA)
+    print(f"  prescribed n={n}: eig err={err:.2e} res={res:.2e} orth={orth:.2e}", flush=True)
+    assert err <= TOL_EIG and res <= TOL_RES and orth <= TOL_ORTH
+
+
+@pytest.mark.parametrize("reduction", [1, 2])
+def test_one_stage_routes_workspace_contents(h, reduction):
+    """NaN-filled versus zeroed workspace, bitwise equal, for both one-stage
+    routes (a ragged last panel included)."""
+    import torch
+    from paper_1912_04062_amd import skewevd
+    print(f"workspace NaN vs zero, reduction {reduction}", flush=True)
+    Ad = to_dev(wl.random_skew(333, 97))
+    outs = []
+    for dbg in (skewevd.DEBUG_NAN_WS, skewevd.DEBUG_ZERO_WS):
+        lam, zr, zi = h.solve(Ad, opts=skewevd.default_opts(reduction=reduction, debug=dbg))
+        torch.cuda.synchronize()
+        outs.append((lam.clone(), zr.clone(), zi.clone()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    assert bool(torch.isfinite(outs[0][1]).all())
+
+
+@pytest.mark.parametrize("reduction", [1, 2])
+def test_one_stage_argument_rules(h, reduction):
+    from paper_1912_04062_amd import skewevd
+    A = to_dev(wl.random_skew(100, 5))
+    for kw in ({"precision": "fp32"}, {"band": 32}):
+        h.solve(A, opts=skewevd.default_opts(reduction=reduction, **kw), check=False)
+        assert h.last_status == -11, kw
+    _, _, st = h.solve_batched([A], reduction=reduction)
+    assert st == -10
