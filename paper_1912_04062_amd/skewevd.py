@@ -208,8 +208,9 @@ class Handle:
             self._lib.skew_evd_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be None at exit)
+        if _finalizing():
             return          # the runtime may be gone; _close_all ran before this
         try:
             self.close()
