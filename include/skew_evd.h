@@ -211,8 +211,14 @@ int skew_evd(int n, const double *A, int lda, int nev,
  * Problems up to n = 4096 are solved together: their stages run side by side
  * on 16 streams of the handle (HIP maps streams onto GPU_MAX_HW_QUEUES
  * hardware queues per process, 4 unless the environment sets more; 16 lets
- * them all run at once) and one bulge-chase launch serves all bands.
- * The precision form is solved one problem at a time with skew_evd_ex.
+ * them all run at once) and one bulge-chase launch serves all bands.  Their
+ * launches are captured as a HIP graph on the first call of a batch
+ * signature (every n, nev, band, input and output pointer and lda) and the
+ * graph is replayed by later calls with the same signature, which saves the
+ * host the enqueueing of each launch; the handle keeps the graph of the last
+ * signature.  A replay reads the inputs present at its addresses when it
+ * runs.  Larger problems, and problems whose spectrum holds a degenerate
+ * cluster (flagged on the device), are solved one by one after the batch.
  * status[i] (host) receives each problem's status; the return value is the
  * first non-zero status (or a negative argument error: -2 count, -3 n,
  * -4 A, -5 lda, -6 nev, -7 lambda, -8 Z_re, -9 Z_im, -12 status).  With

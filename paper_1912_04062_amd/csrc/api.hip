@@ -83,6 +83,15 @@ struct skew_evd_handle_s {
     hipEvent_t bev0 = nullptr;
     char *bhost = nullptr;
     size_t bhost_cap = 0;
+    // the batch's launches as a HIP graph, captured on bstream for one batch
+    // signature (bkey) and replayed while the signature repeats; the
+    // generations change whenever the workspace or the pinned descriptors
+    // are reallocated (an address can be reused)
+    hipStream_t bstream = nullptr;
+    hipEvent_t bgev[2] = {};
+    hipGraphExec_t bgraph = nullptr;
+    std::vector<uintptr_t> bkey;
+    unsigned long ws_gen = 0, bhost_gen = 0;
     // band-width autotuner: (precision, size class) -> (band, best wall ms)
     struct Tuned {
         int band, panel;
@@ -285,6 +294,7 @@ int ensure_ws(skew_evd_handle h, size_t bytes, size_t limit)
         return SKEW_EVD_ERR_NOMEM;
     }
     h->ws_bytes = bytes;
+    ++h->ws_gen;
     return SKEW_EVD_OK;
 }
 
@@ -1236,6 +1246,13 @@ int skew_evd_destroy(skew_evd_handle h)
     for (auto e : h->bev) (void)hipEventDestroy(e);
     if (h->bev0) (void)hipEventDestroy(h->bev0);
     if (h->bhost) (void)hipHostFree(h->bhost);
+    if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
+    if (h->bstream) {
+        (void)hipStreamSynchronize(h->bstream);
+        (void)hipStreamDestroy(h->bstream);
+    }
+    for (auto e : h->bgev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return SKEW_EVD_OK;
 }
@@ -1526,23 +1543,26 @@ int ensure_streams(skew_evd_handle h, int S)
         h->bev.push_back(e);
     }
     if (!h->bev0) HCHK(hipEventCreateWithFlags(&h->bev0, hipEventDisableTiming));
+    if (!h->bstream) HCHK(hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking));
+    for (auto &e : h->bgev)
+        if (!e) HCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return SKEW_EVD_OK;
 }
 
-// the sub-streams 0..S-1 wait for the work queued on h->stream
-int fork_streams(skew_evd_handle h, int S)
+// the sub-streams 0..S-1 wait for the work queued on ms
+int fork_streams(skew_evd_handle h, hipStream_t ms, int S)
 {
-    HCHK(hipEventRecord(h->bev0, h->stream));
+    HCHK(hipEventRecord(h->bev0, ms));
     for (int k = 0; k < S; ++k) HCHK(hipStreamWaitEvent(h->sub_streams[k], h->bev0, 0));
     return SKEW_EVD_OK;
 }
 
-// h->stream waits for the work queued on the sub-streams 0..S-1
-int join_streams(skew_evd_handle h, int S)
+// ms waits for the work queued on the sub-streams 0..S-1
+int join_streams(skew_evd_handle h, hipStream_t ms, int S)
 {
     for (int k = 0; k < S; ++k) {
         HCHK(hipEventRecord(h->bev[k], h->sub_streams[k]));
-        HCHK(hipStreamWaitEvent(h->stream, h->bev[k], 0));
+        HCHK(hipStreamWaitEvent(ms, h->bev[k], 0));
     }
     return SKEW_EVD_OK;
 }
@@ -1598,11 +1618,16 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
     const size_t hbytes = sizeof(skew::ChaseProb) * cnt + sizeof(int) * (M + 1 + 2 * cnt) +
                           sizeof(unsigned) * (2 * cnt + 2);
     if (hbytes > h->bhost_cap) {
-        if (h->bhost) HCHK(hipHostFree(h->bhost));
+        if (h->bhost) {
+            // a replay of the previous batch may still read the old images
+            HCHK(hipStreamSynchronize(h->bstream));
+            HCHK(hipHostFree(h->bhost));
+        }
         h->bhost = nullptr;
         h->bhost_cap = 0;
         HCHK(hipHostMalloc((void **)&h->bhost, hbytes, hipHostMallocDefault));
         h->bhost_cap = hbytes;
+        ++h->bhost_gen;
     }
     skew::ChaseProb *hp = (skew::ChaseProb *)h->bhost;
     int *hl = (int *)(hp + cnt);
@@ -1632,49 +1657,100 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
     skew::ChaseProb *dprobs = (skew::ChaseProb *)(h->ws + probs_off);
     int *dlanes = (int *)(h->ws + lanes_off);
     unsigned *dstat = (unsigned *)(h->ws + stat_off);
-    HCHK(hipMemcpyAsync(dprobs, hp, sizeof(skew::ChaseProb) * cnt, hipMemcpyHostToDevice, h->stream));
-    HCHK(hipMemcpyAsync(dlanes, hl, sizeof(int) * (M + 1 + 2 * cnt), hipMemcpyHostToDevice, h->stream));
-    skew::launch_fill32(dstat, 0u, 2 * (size_t)cnt + 2, h->stream);
-    std::vector<skew_evd_handle_s *> views(cnt);
-    for (int s2 = 0; s2 < S; ++s2)
-        for (int k : part[s2]) views[k] = make_view(h, it[k], h->sub_streams[s2]);
-    // One host thread enqueues everything, taking the streams in turn (problem
-    // r of every stream, then problem r + 1, ...): the device starts on the
-    // first problems while the rest are enqueued.  (With one enqueueing thread
-    // per stream, the launches of several threads met inside the runtime, and
-    // a profiler's interception of them crashed.)
-    std::vector<int> src(S, SKEW_EVD_OK);
-    size_t rounds = 0;
-    for (int s2 = 0; s2 < S; ++s2) rounds = std::max(rounds, part[s2].size());
-    auto run_parts = [&](bool first) {
-        for (size_t r = 0; r < rounds; ++r)
-            for (int s2 = 0; s2 < S; ++s2) {
-                if (r >= part[s2].size() || src[s2]) continue;
-                const int k = part[s2][r], i = it[k].idx;
-                src[s2] = first ? batch_part_a(views[k], it[k], A[i], lda[i])
-                                : batch_part_c(views[k], it[k], lambda[i], Z_re[i], Z_im[i], dstat + 2 * k);
+    // The launch sequence depends on nothing but this key.  Its first call
+    // captures the sequence as a HIP graph (on bstream, which can be
+    // captured whatever h->stream is); later calls with the same key replay
+    // the graph, which spares the host the enqueueing of every launch.
+    std::vector<uintptr_t> key = {(uintptr_t)h->ws,   (uintptr_t)h->ws_gen, (uintptr_t)h->bhost,
+                                  (uintptr_t)h->bhost_gen, (uintptr_t)cnt, (uintptr_t)S,
+                                  (uintptr_t)M,       (uintptr_t)maxlen};
+    for (int k = 0; k < cnt; ++k) {
+        const int i = it[k].idx;
+        const Plan &p = it[k].p;
+        for (uintptr_t x : {(uintptr_t)p.n, (uintptr_t)p.nev, (uintptr_t)p.b, (uintptr_t)p.hh_panels,
+                            (uintptr_t)A[i], (uintptr_t)lda[i], (uintptr_t)lambda[i], (uintptr_t)Z_re[i],
+                            (uintptr_t)Z_im[i], (uintptr_t)it[k].off})
+            key.push_back(x);
+    }
+    const hipStream_t ms = h->bstream;
+    if (!(h->bgraph && key == h->bkey)) {
+        if (h->bgraph) {
+            HCHK(hipStreamSynchronize(ms));
+            HCHK(hipGraphExecDestroy(h->bgraph));
+            h->bgraph = nullptr;
+            h->bkey.clear();
+        }
+        std::vector<skew_evd_handle_s *> views(cnt);
+        for (int s2 = 0; s2 < S; ++s2)
+            for (int k : part[s2]) views[k] = make_view(h, it[k], h->sub_streams[s2]);
+        // One host thread enqueues everything, taking the streams in turn
+        // (problem r of every stream, then problem r + 1, ...).  (With one
+        // enqueueing thread per stream, the launches of several threads met
+        // inside the runtime, and a profiler's interception of them crashed.)
+        std::vector<int> src(S, SKEW_EVD_OK);
+        size_t rounds = 0;
+        for (int s2 = 0; s2 < S; ++s2) rounds = std::max(rounds, part[s2].size());
+        auto run_parts = [&](bool first) {
+            for (size_t r = 0; r < rounds; ++r)
+                for (int s2 = 0; s2 < S; ++s2) {
+                    if (r >= part[s2].size() || src[s2]) continue;
+                    const int k = part[s2][r], i = it[k].idx;
+                    src[s2] = first ? batch_part_a(views[k], it[k], A[i], lda[i])
+                                    : batch_part_c(views[k], it[k], lambda[i], Z_re[i], Z_im[i], dstat + 2 * k);
+                }
+        };
+        auto enqueue = [&]() -> int {
+            HCHK(hipMemcpyAsync(dprobs, hp, sizeof(skew::ChaseProb) * cnt, hipMemcpyHostToDevice, ms));
+            HCHK(hipMemcpyAsync(dlanes, hl, sizeof(int) * (M + 1 + 2 * cnt), hipMemcpyHostToDevice, ms));
+            skew::launch_fill32(dstat, 0u, 2 * (size_t)cnt + 2, ms);
+            int r2 = fork_streams(h, ms, S);
+            if (r2) return r2;
+            run_parts(true);
+            r2 = join_streams(h, ms, S);
+            for (int s2 = 0; s2 < S && !r2; ++s2) r2 = src[s2];
+            if (r2) return r2;
+            const int G = std::max(1, std::min(skew::chase_max_workgroups(), 8 * M));
+            HCHK(skew::launch_chase_batched(dprobs, dlanes, M, maxlen, G, dstat + 2 * cnt, ms));
+            r2 = fork_streams(h, ms, S);
+            if (r2) return r2;
+            run_parts(false);
+            r2 = join_streams(h, ms, S);
+            for (int s2 = 0; s2 < S && !r2; ++s2) r2 = src[s2];
+            return r2;
+        };
+        HCHK(hipStreamBeginCapture(ms, hipStreamCaptureModeRelaxed));
+        rc = enqueue();
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ms, &g);
+        for (auto v : views) delete v;
+        if (!rc && ec != hipSuccess) {
+            snprintf(g_errtext, sizeof(g_errtext), "capture of the batch: %s", hipGetErrorString(ec));
+            rc = SKEW_EVD_ERR_HIP;
+        }
+        if (!rc) {
+            const hipError_t ei = hipGraphInstantiate(&h->bgraph, g, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                snprintf(g_errtext, sizeof(g_errtext), "instantiation of the batch graph: %s",
+                         hipGetErrorString(ei));
+                h->bgraph = nullptr;
+                rc = SKEW_EVD_ERR_HIP;
             }
-    };
-    rc = fork_streams(h, S);
-    if (!rc) {
-        run_parts(true);
-        rc = join_streams(h, S);
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) {
+            (void)hipGetLastError();
+            return rc;
+        }
+        h->bkey = key;
     }
-    for (int s2 = 0; s2 < S && !rc; ++s2) rc = src[s2];
-    if (!rc) {
-        const int G = std::max(1, std::min(skew::chase_max_workgroups(), 8 * M));
-        HCHK(skew::launch_chase_batched(dprobs, dlanes, M, maxlen, G, dstat + 2 * cnt, h->stream));
-        rc = fork_streams(h, S);
-    }
-    if (!rc) {
-        run_parts(false);
-        rc = join_streams(h, S);
-    }
-    for (int s2 = 0; s2 < S && !rc; ++s2) rc = src[s2];
-    for (auto v : views) delete v;
-    if (!rc) HCHK(hipMemcpyAsync(hs, dstat, sizeof(unsigned) * 2 * cnt, hipMemcpyDeviceToHost, h->stream));
+    // ordered after the work already on h->stream, and h->stream after it
+    HCHK(hipEventRecord(h->bgev[0], h->stream));
+    HCHK(hipStreamWaitEvent(ms, h->bgev[0], 0));
+    HCHK(hipGraphLaunch(h->bgraph, ms));
+    HCHK(hipEventRecord(h->bgev[1], ms));
+    HCHK(hipStreamWaitEvent(h->stream, h->bgev[1], 0));
+    HCHK(hipMemcpyAsync(hs, dstat, sizeof(unsigned) * 2 * cnt, hipMemcpyDeviceToHost, h->stream));
     HCHK(hipStreamSynchronize(h->stream));
-    if (rc) return rc;
     for (int k = 0; k < cnt; ++k) {
         const int i = it[k].idx;
         if (hs[2 * k] & 1u) status[i] = SKEW_EVD_ERR_NONFINITE;

@@ -146,8 +146,9 @@ __global__ __launch_bounds__(CT) void k_h_col(const double *__restrict__ Hr, con
 }
 
 // Prow: per tile (I, J) 128 doubles (real parts, then imaginary parts);
-// Pcol: per strip (J, s) 128 doubles; Ps: per tile one double; Pd: per row
-// block 256 doubles (Re, Im of V^H v, then Re, Im of W^H v, 64 each).
+// Pcol: per strip (J, s) 128 doubles; Ps: per workgroup (strip) one double,
+// the sum of its tiles' scalars; Pd: per row block 256 doubles (Re, Im of
+// V^H v, then Re, Im of W^H v, 64 each).
 __global__ __launch_bounds__(256) void k_h_hemv(const double *__restrict__ Hr, const double *__restrict__ Hi,
                                                 int lda, int r, int m, const double *__restrict__ vr,
                                                 const double *__restrict__ vi, const double *__restrict__ Vr,
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void k_h_hemv(const double *__restrict__ Hr, c
     if (tid < OT) vJr[tid] = (j0 + tid < m) ? vr[j0 + tid] : 0.0;
     else if (tid < 2 * OT) vJi[tid - OT] = (j0 + tid - OT < m) ? vi[j0 + tid - OT] : 0.0;
     const double *Ar = Hr + (size_t)r * lda + r, *Ai = Hi + (size_t)r * lda + r;
-    double csr[16], csi[16];
+    double csr[16], csi[16], scs = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) csr[q] = csi[q] = 0.0;
     for (int I = Ib; I < Ie; ++I) {
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_h_hemv(const double *__restrict__ Hr, c
             yi = fma(dg, ui, yi);
             Prow[t * 128 + tx] = yr;
             Prow[t * 128 + 64 + tx] = yi;
-            if (tx == 0) Ps[t] = sc;
+            scs += sc;
         }
         if (I == J) {
             // partial dots over the block's 64 rows: wave w takes k = w, w + 4,
@@ -244,12 +245,13 @@ __global__ __launch_bounds__(256) void k_h_hemv(const double *__restrict__ Hr, c
             pc[64 + ty + 4 * q] = b;
         }
     }
+    if (tid == 0) Ps[blockIdx.x] = scs;
 }
 
 // D: [0, 64) Re D1, [64, 128) Im D1, [128, 192) Re D2, [192, 256) Im D2,
 // D[256] = alpha.  T: real and imaginary planes, column-major, ldt = 64.
 __global__ __launch_bounds__(256) void k_h_dots(const double *__restrict__ Pd, int nt, const double *__restrict__ Ps,
-                                                int ntiles, int jj, const double *__restrict__ tau,
+                                                int nps, int jj, const double *__restrict__ tau,
                                                 double *__restrict__ D, double *__restrict__ Tr,
                                                 double *__restrict__ Ti)
 {
@@ -271,9 +273,14 @@ __global__ __launch_bounds__(256) void k_h_dots(const double *__restrict__ Pd, i
     }
     dv[tid] = a0 + a1;
     D[tid] = a0 + a1;
-    double sc = 0.0;
-    for (int t = tid; t < ntiles; t += 256) sc += Ps[t];
-    red[tid] = sc;
+    double sc0 = 0.0, sc1 = 0.0;
+    int t = tid;
+    for (; t + 256 < nps; t += 512) {
+        sc0 += Ps[t];
+        sc1 += Ps[t + 256];
+    }
+    if (t < nps) sc0 += Ps[t];
+    red[tid] = sc0 + sc1;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (tid < o) red[tid] += red[tid + o];
@@ -513,8 +520,8 @@ void launch_herm_panel(double *Hr, double *Hi, int lda, int n, int c0, int nb, d
                            (const double *)(Vr + o), (const double *)(Vi + o), (const double *)Vr,
                            (const double *)Vi, (const double *)Wr, (const double *)Wi, ldv, off, jj, Prow, Pcol, Ps,
                            Pd);
-        hipLaunchKernelGGL(k_h_dots, dim3(1), dim3(256), 0, st, (const double *)Pd, nt, (const double *)Ps,
-                           nt * (nt + 1) / 2, jj, (const double *)tau, D, Tr, Ti);
+        hipLaunchKernelGGL(k_h_dots, dim3(1), dim3(256), 0, st, (const double *)Pd, nt, (const double *)Ps, nwg, jj,
+                           (const double *)tau, D, Tr, Ti);
         hipLaunchKernelGGL(k_h_w, dim3(nt), dim3(256), 0, st, (const double *)Hr, (const double *)Hi, lda, r, m, nt,
                            (const double *)Prow, (const double *)Pcol, (const double *)D, Vr, Vi, Wr, Wi, ldv, off,
                            jj, (const double *)tau, (int)(jj + 1 < nb));

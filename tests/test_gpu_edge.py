@@ -146,6 +146,45 @@ def test_batched_precision_form():
     pass
 
 
+def test_batched_graph_replays(h):
+    """The batched form captures its launches as a HIP graph on the first call
+    of a batch signature and replays it on later calls with the same inputs
+    and outputs.  Three calls in a row, with the program's own eager work
+    (single solves of the same problems) and synchronizations between them:
+    every replay bitwise equal to the single solves.  A call with other
+    output buffers captures a new graph, with the same results."""
+    import torch
+    from paper_1912_04062_amd import skewevd
+    print("batched graph replays", flush=True)
+    sizes = [5, 64, 65, 130, 200, 257, 300, 511, 64, 900]
+    mats = [wl.random_skew(n, 610 + k) for k, n in enumerate(sizes)]
+    dev = [to_dev(A) for A in mats]
+    ref = []
+    for Ad in dev:
+        l1, r1, i1 = h.solve(Ad)
+        ref.append((l1.clone(), r1.clone(), i1.clone()))
+    torch.cuda.synchronize()
+    out = h.batched_outputs(dev)
+    for rep in range(3):
+        for o in out:                     # stale contents must not matter
+            for t in o:
+                t.fill_(float("nan"))
+        res, status, st = h.solve_batched(dev, out=out)
+        torch.cuda.synchronize()
+        assert st == 0 and all(x == 0 for x in status), (rep, status)
+        for k, ((lam, zr, zi), (l1, r1, i1)) in enumerate(zip(res, ref)):
+            assert torch.equal(lam, l1) and torch.equal(zr, r1) and torch.equal(zi, i1), (rep, k)
+        # eager work between the replays
+        l2, _, _ = h.solve(dev[3])
+        torch.cuda.synchronize()
+        assert torch.equal(l2, ref[3][0])
+    res, status, st = h.solve_batched(dev)          # fresh outputs: a new capture
+    torch.cuda.synchronize()
+    assert st == 0
+    for k, ((lam, zr, zi), (l1, r1, i1)) in enumerate(zip(res, ref)):
+        assert torch.equal(lam, l1) and torch.equal(zr, r1) and torch.equal(zi, i1), k
+
+
 def test_batched_mixed_problems(h):
     """One batched call over problems of every kind: tiny orders, a partial
     spectrum, an order above the batched path's limit (solved on its own), a
