@@ -270,7 +270,8 @@ class Handle:
                  empty_colmajor(max(x, 1), max(v, 1), dev),
                  empty_colmajor(max(x, 1), max(v, 1), dev)) for x, v in zip(ns, nevs)]
 
-    def solve_batched(self, mats, precision="fp64", band=0, autotune=0, nevs=None, reduction=0, out=None):
+    def solve_batched(self, mats, precision="fp64", band=0, autotune=0, nevs=None, reduction=0, out=None,
+                      panel_method=0):
         """Solve a list of skew matrices (each n_i x n_i float64 CUDA); returns
         a list of (lam, Zre, Zim), the per-problem status list and the call's
         status.  nevs: eigenpairs per problem (default ceil(n_i / 2)).  out:
@@ -292,7 +293,7 @@ class Handle:
         zr_a = PtrA(*[o[1].data_ptr() for o in outs])
         zi_a = PtrA(*[o[2].data_ptr() for o in outs])
         status = IntA()
-        o = default_opts(precision, band, autotune=autotune, reduction=reduction)
+        o = default_opts(precision, band, autotune=autotune, reduction=reduction, panel_method=panel_method)
         inf = Info()
         st = self._lib.skew_evd_batched(self._h, count, n_a, A_a, lda_a, nev_a, l_a, zr_a, zi_a,
                                         ctypes.byref(o), ctypes.byref(inf), status)
