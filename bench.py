@@ -56,6 +56,19 @@ def useful_flops(n, nev):
     return 4.0 / 3.0 * n ** 3 + 8.0 * n * n * nev
 
 
+def host_cpu():
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(sample_n=3072):
     import oracle
     from paper_1912_04062_amd import workloads
@@ -67,8 +80,8 @@ def cpu_baseline(sample_n=3072):
     return {"value": f / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"one full oracle solve of a random skew matrix n={sample_n} "
-                      f"(nev={(sample_n + 1) // 2}), {dt:.1f} s; TFLOP/s with the same useful-flop "
-                      f"count F(n) as the GPU line"}
+                      f"(nev={(sample_n + 1) // 2}), {dt:.1f} s on {host_cpu()}; TFLOP/s with the same "
+                      f"useful-flop count F(n) as the GPU line"}
 
 
 def accuracy(Ad, lam, zr, zi):

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/skew_evd.h"
@@ -446,11 +447,18 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
             double *cq = ptr<double>(h, L.cq), *Gq = ptr<double>(h, L.cqGp);
             unsigned *qf = ctl + CTL_QRFLAG;
             const size_t BB = (size_t)64 * 64;
-            int S = skew::launch_gemm_tn_part<T>(P, n, P, n, b, b, m, Gq, st, cholqr_splits(m));
+            // the Gram matrices (the reflectors' norms) are formed in FP64 in both forms
+            auto gram = [&](const T *X, int ldx) -> int {
+                if constexpr (std::is_same<T, float>::value)
+                    return skew::launch_gemm_tn_part_f64(X, ldx, X, ldx, b, b, m, Gq, st, cholqr_splits(m));
+                else
+                    return skew::launch_gemm_tn_part<T>(X, ldx, X, ldx, b, b, m, Gq, st, cholqr_splits(m));
+            };
+            int S = gram(P, n);
             skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
             skew::launch_chol_qr(b, 1, cq, qf, st);
             skew::launch_gemm_nn<T>(P, n, cq + skew::CQ_R1INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
-            S = skew::launch_gemm_tn_part<T>(Vq, m, Vq, m, b, b, m, Gq, st, cholqr_splits(m));
+            S = gram(Vq, m);
             skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
             skew::launch_chol_qr(b, 2, cq, qf, st);
             skew::launch_gemm_nn<T>(Vq, m, cq + skew::CQ_R2INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);

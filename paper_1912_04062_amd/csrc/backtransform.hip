@@ -704,17 +704,19 @@ __global__ __launch_bounds__(256) void k_merge_t(const double *__restrict__ T1, 
 }
 
 // Cpart[s] = A[kb:ke, 0:M]^T B[kb:ke, 0:N]   (A: K x M, B: K x N, column-major)
-template <typename T, int TM, int TN>
-__global__ __launch_bounds__(256) GEMM_OCC2 void k_gemm_tn_part(const T *__restrict__ A, int lda, const T *__restrict__ B,
-                                                      int ldb, int M, int N, int K, int kchunk,
-                                                      double *__restrict__ Cpart)
+// TL: the element type in memory (float operands can be multiplied and
+// summed in FP64 with T = double: the FP32 form's panel Gram matrices)
+template <typename T, int TM, int TN, typename TL = T>
+__global__ __launch_bounds__(256) GEMM_OCC2 void k_gemm_tn_part(const TL *__restrict__ A, int lda,
+                                                      const TL *__restrict__ B, int ldb, int M, int N, int K,
+                                                      int kchunk, double *__restrict__ Cpart)
 {
     extern __shared__ char smraw[];
     T *smem = (T *)smraw;
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN, s = blockIdx.z;
     const int kb = s * kchunk, ke = min(K, kb + kchunk);
-    auto fa = [=](int i, int k) -> T { return (i < M && k < ke) ? A[(size_t)i * lda + k] : T(0); };
-    auto fb = [=](int j, int k) -> T { return (j < N && k < ke) ? B[(size_t)j * ldb + k] : T(0); };
+    auto fa = [=](int i, int k) -> T { return (i < M && k < ke) ? (T)A[(size_t)i * lda + k] : T(0); };
+    auto fb = [=](int j, int k) -> T { return (j < N && k < ke) ? (T)B[(size_t)j * ldb + k] : T(0); };
     gemm::Acc<T, TM, TN> acc;
     acc.zero();
     gemm::kloop<T, TM, TN, true, true>(fa, fb, m0, n0, kb, ke, smem, acc);
@@ -866,6 +868,20 @@ int tn_splits(int K, int tiles)
     if (S > maxS) S = maxS;
     if (S > 32) S = 32;
     if (S < 1) S = 1;
+    return S;
+}
+
+int launch_gemm_tn_part_f64(const float *A, int lda, const float *B, int ldb, int M, int N, int K, double *Cpart,
+                            hipStream_t st, int S_req)
+{
+    const int TM = 64, TN = 64;
+    unsigned tiles = cdiv(M, TM) * cdiv(N, TN);
+    int S = S_req > 0 ? S_req : tn_splits(K, (int)tiles);
+    int kc = (int)(cdiv(cdiv(K, S), 16) * 16);
+    S = (int)cdiv(K, kc);
+    dim3 grid(cdiv(M, TM), cdiv(N, TN), S);
+    hipLaunchKernelGGL((k_gemm_tn_part<double, 64, 64, float>), grid, dim3(256), (gemm::smem_bytes<double, 64, 64>()),
+                       st, A, lda, B, ldb, M, N, K, kc, Cpart);
     return S;
 }
 

@@ -89,6 +89,9 @@ int tn_splits(int K, int tiles);
 template <typename T>
 int launch_gemm_tn_part(const T *A, int lda, const T *B, int ldb, int M, int N, int K, double *Cpart,
                         hipStream_t st, int S_req = 0);
+// the same for FP32 operands with FP64 products and sums
+int launch_gemm_tn_part_f64(const float *A, int lda, const float *B, int ldb, int M, int N, int K, double *Cpart,
+                            hipStream_t st, int S_req = 0);
 template <typename T>
 void launch_gemm_nn(const T *A, int lda, const double *Bpart, int S, int M, int N, int K, T *C, int ldc,
                     double alpha, int beta, hipStream_t st);
