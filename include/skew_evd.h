@@ -57,6 +57,10 @@ extern "C" {
 #define SKEW_EVD_PREC_FP64 0        /* every stage in FP64 */
 #define SKEW_EVD_PREC_FP32_REFINE 1 /* band reduction and back-transformation in FP32
                                        (FP32 MFMA, FP64 norms), then FP64 refinement */
+#define SKEW_EVD_PREC_BF16_REFINE 2 /* not built: refused as an argument error.  A BF16
+                                       reduction starts the refinement about 0.03 from the
+                                       eigenpairs at n = 16384, beyond the Newton step's reach
+                                       for every pair (the FP32 start is 4.5e-7) */
 
 typedef struct skew_evd_opts {
     int precision;          /* SKEW_EVD_PREC_*; default FP64 */
@@ -83,8 +87,15 @@ typedef struct skew_evd_opts {
                                choice with opts.autotune, else a fixed rule by n) */
     int reduction;          /* SKEW_EVD_REDUCE_TWO_STAGE (default), SKEW_EVD_REDUCE_ONE_STAGE or
                                SKEW_EVD_REDUCE_COMPLEX_HERMITIAN */
-    int reserved[1];
+    int tridiag_method;     /* SKEW_EVD_TRIDIAG_BISECT_INVIT (0, the default and the only
+                               method built); other values are argument errors */
 } skew_evd_opts;
+
+/* Symmetric tridiagonal eigensolver (Algorithm 1, step 2): multisection
+ * bisection on Sturm counts and inverse iteration with Gram-Schmidt across
+ * close eigenvalues (the method the paper names for its BSE runs).  The paper's
+ * ELPA runs use divide and conquer, which is not built. */
+#define SKEW_EVD_TRIDIAG_BISECT_INVIT 0
 
 /* Reduction to tridiagonal form.  TWO_STAGE: full-to-band, then bulge chasing
  * (Section 2.3.2, the ELPA2 route).  ONE_STAGE (Section 2.3.1, the ELPA1 route

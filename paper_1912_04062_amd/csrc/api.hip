@@ -992,6 +992,7 @@ int validate_opts(const skew_evd_opts *o)
 {
     if (!o) return 0;
     if (o->precision != SKEW_EVD_PREC_FP64 && o->precision != SKEW_EVD_PREC_FP32_REFINE) return 1;
+    if (o->tridiag_method != SKEW_EVD_TRIDIAG_BISECT_INVIT) return 1;
     if (o->band != 0 && !band_supported(o->band)) return 1;
     if (o->max_refine_sweeps < 0) return 1;
     if (o->no_fp64_fallback != 0 && o->no_fp64_fallback != 1) return 1;

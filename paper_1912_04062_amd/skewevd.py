@@ -44,7 +44,7 @@ class Opts(ctypes.Structure):
                 ("workspace_limit", ctypes.c_size_t), ("profile", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("no_fp64_fallback", ctypes.c_int),
                 ("debug", ctypes.c_int), ("all_pairs", ctypes.c_int), ("panel_method", ctypes.c_int),
-                ("reduction", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
+                ("reduction", ctypes.c_int), ("tridiag_method", ctypes.c_int)]
 
 
 class KStat(ctypes.Structure):

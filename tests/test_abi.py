@@ -87,7 +87,7 @@ def test_ctypes_structs_match_the_header(tmp_path):
     fields = {"skew_evd_opts": (s.Opts, ["precision", "band", "max_refine_sweeps", "refine_tol",
                                          "workspace_limit", "profile", "autotune",
                                          "no_fp64_fallback", "debug", "all_pairs", "panel_method",
-                                         "reduction", "reserved"]),
+                                         "reduction", "tridiag_method"]),
               "skew_evd_info": (s.Info, ["ms_total", "ms_stage", "band", "refine_sweeps",
                                          "refine_residual", "workspace_bytes", "kern"])}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "skew_evd.h"', "int main(void) {"]

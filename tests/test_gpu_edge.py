@@ -352,6 +352,21 @@ def test_one_stage_routes_workspace_contents(h, reduction):
     assert bool(torch.isfinite(outs[0][1]).all())
 
 
+def test_unbuilt_options_are_argument_errors(h):
+    """The boundary's BF16 precision value and tridiagonal-method values other
+    than bisection + inverse iteration are refused as argument errors."""
+    from paper_1912_04062_amd import skewevd
+    A = to_dev(wl.random_skew(100, 6))
+    h.solve(A, opts=skewevd.default_opts(precision=2), check=False)
+    assert h.last_status == -11
+    o = skewevd.default_opts()
+    o.tridiag_method = 1
+    h.solve(A, opts=o, check=False)
+    assert h.last_status == -11
+    lam, _, _ = h.solve(A)                   # the handle still works
+    assert np.isfinite(lam.cpu().numpy()).all()
+
+
 @pytest.mark.parametrize("reduction", [1, 2])
 def test_one_stage_argument_rules(h, reduction):
     from paper_1912_04062_amd import skewevd
