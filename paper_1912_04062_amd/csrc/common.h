@@ -39,7 +39,8 @@ __device__ __forceinline__ unsigned ld_acquire(const unsigned *p)
 }
 __device__ __forceinline__ unsigned ld_relaxed(const unsigned *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const __attribute__((address_space(1))) unsigned *)p, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_release(unsigned *p, unsigned v)
 {
@@ -53,17 +54,21 @@ __device__ __forceinline__ void add_release(unsigned *p, unsigned v)
 // Coherent (agent-scope, relaxed) element accesses for data exchanged between
 // workgroups inside one kernel: they bypass the per-XCD caches' stale lines
 // without the whole-cache write-back/invalidate that agent-scope fences cost.
+// (The pointers are cast to the global address space: a generic pointer
+// would make these flat accesses, which also count against the LDS counter.)
+typedef __attribute__((address_space(1))) double gbl_double;
+typedef __attribute__((address_space(1))) unsigned gbl_unsigned;
 __device__ __forceinline__ double ld_coh(const double *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const gbl_double *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh(double *p, double v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((gbl_double *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_relaxed(unsigned *p, unsigned v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((gbl_unsigned *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wait for this wave's outstanding vector memory operations (s_waitcnt
