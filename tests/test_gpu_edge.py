@@ -316,6 +316,57 @@ def test_complex_hermitian_route(h, n):
     _route_vs_oracle(h, wl.random_skew(n, 1900 + n), 2, "complex")
 
 
+@pytest.mark.parametrize("reduction", [1, 2])
+def test_one_stage_routes_partial_padded_all_pairs(h, reduction):
+    """Both one-stage routes with a partial spectrum, with padded leading
+    dimensions (bitwise equal to the unpadded solve, padding never read or
+    written), and with every eigenpair (both signs)."""
+    import oracle
+    import torch
+    from paper_1912_04062_amd import skewevd
+    n = 301
+    print(f"routes: partial/padded/all pairs, reduction {reduction}", flush=True)
+    A = wl.random_skew(n, 2300 + reduction)
+    lref, _ = oracle.skew_evd(A)
+    nA = lref.max()
+    o = skewevd.default_opts(reduction=reduction)
+    # partial spectrum: the nev smallest non-negative eigenvalues
+    lam, zr, zi = h.solve(to_dev(A), nev=40, opts=o)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(lam.cpu().numpy() - lref[:40])) <= TOL_EIG * nA
+    c = dev_checks(to_dev(A), lam, zr, zi, nA=nA)
+    assert c["colres"] <= 1e-12 and c["orth_max"] <= 1e-12, c
+    # padded leading dimensions
+    big = np.full((n + 5, n + 3), np.nan, order="F")
+    big[:n, :n] = A
+    Av = to_dev(big)[:n, :n]
+    nev = (n + 1) // 2
+    lamp = torch.empty(nev, dtype=torch.float64, device="cuda")
+    zrp = skewevd.empty_colmajor(n + 7, nev, "cuda")
+    zip_ = skewevd.empty_colmajor(n + 11, nev, "cuda")
+    zrp.fill_(7.0)
+    zip_.fill_(-7.0)
+    l1, r1, i1 = h.solve(Av, out=(lamp, zrp[:n], zip_[:n]), opts=o)
+    l0, r0, i0 = h.solve(to_dev(A), opts=o)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l0) and torch.equal(r1, r0) and torch.equal(i1, i0)
+    assert bool((zrp[n:] == 7.0).all()) and bool((zip_[n:] == -7.0).all())
+    # every eigenpair: signed values ascending, conj vectors for the negative half
+    oa = skewevd.default_opts(reduction=reduction, all_pairs=1)
+    la, ra, ia = h.solve(to_dev(A), opts=oa)
+    torch.cuda.synchronize()
+    mu = la.cpu().numpy()
+    ref = np.concatenate([-lref[::-1][: n - len(lref)], lref])
+    assert np.all(np.diff(mu) >= 0)
+    assert np.max(np.abs(mu - ref)) <= TOL_EIG * nA
+    Z = ra.cpu().numpy() + 1j * ia.cpu().numpy()
+    Af = np.tril(A, -1) - np.tril(A, -1).T
+    R = Af @ Z - Z * (1j * mu)[None, :]
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-12 * nA
+    G = Z.conj().T @ Z - np.eye(n)
+    assert np.max(np.abs(G)) <= 1e-12
+
+
 def test_complex_hermitian_route_prescribed(h):
     """Known spectrum with close pairs (prescribed l_k) through the complex
     route: every eigenvalue against l_k."""
