@@ -156,7 +156,7 @@ Layout plan_layout(const Plan &p)
     L.Ypart = take(es * 16 * m0 * b);
     L.Y0 = take(es * m0 * b);
     L.Wd = take(es * m0 * b);
-    L.Gp = take(sizeof(double) * (m0 / 512 + 2) * b * b);
+    L.Gp = take(sizeof(double) * (m0 / skew::gram_chunk_rows() + 2) * b * b);
     L.Tx = take(es * 2 * b * b);
     L.part = take(sizeof(double) * skew::panel_qr_part_doubles((int)m0, (int)b));
     L.ab = take(sizeof(double) * (2 * b + 1) * n);
@@ -227,7 +227,7 @@ Layout plan_layout(const Plan &p)
 }
 
 // control words
-enum { CTL_FLAGS = 0, CTL_ERR = 1, CTL_BAR = 2, CTL_QRFLAG = 3, CTL_HHHAND = 4, CTL_PROGRESS = 64 };
+enum { CTL_FLAGS = 0, CTL_ERR = 1, CTL_BAR = 2, CTL_QRFLAG = 3, CTL_PROGRESS = 64 };
 
 // Fixed band rule (opts.band = 0 without the autotuner).  The autotuner
 // picks 64 for every size class from 128 to 1024 on gfx950: the wider panels'
@@ -462,7 +462,7 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
             skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
             skew::launch_chol_qr(b, 2, cq, qf, st);
             skew::launch_gemm_nn<T>(Vq, m, cq + skew::CQ_R2INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
-            skew::launch_hh_rebuild<T>(Vq, m, b, P, n, cq, Tf, tauj, qf, ctl + CTL_HHHAND, ctl + CTL_ERR, st);
+            skew::launch_hh_rebuild<T>(Vq, m, b, P, n, cq, Tf, tauj, qf, st);
             if (m > b)
                 skew::launch_gemm_nn<T>(Vq + b, m, cq + skew::CQ_UINV * BB, 1, m - b, b, b, Vq + b, m, 1.0, 0, st);
             skip = qf;
@@ -626,7 +626,7 @@ int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, 
         for (int pass = 0; wl > 0 && pass < passes; ++pass) {
             const double *Qw = Q + (size_t)w0 * ldq;
             int S = skew::launch_gemm_tn_part<double>(Qw, ldq, Qb, ldq, wl, nb, n, ptr<double>(h, L.Pp), st);
-            skew::launch_reduce_left(nullptr, ptr<double>(h, L.Pp), S, wl, nb, ptr<double>(h, L.P), st);
+            skew::launch_gram_reduce(ptr<double>(h, L.Pp), S, wl * nb, ptr<double>(h, L.P), st);
             skew::launch_gemm_nn<double>(Qw, ldq, ptr<double>(h, L.P), 1, n, nb, wl, Qb, ldq, -1.0, 1, st);
         }
         int S = skew::launch_gemm_tn_part<double>(Qb, ldq, Qb, ldq, nb, nb, n, ptr<double>(h, L.Gp2), st);

@@ -254,8 +254,18 @@ template <typename T>
 __global__ void k_ysum(const T *__restrict__ Ypart, int S, size_t len, T *__restrict__ Y0)
 {
     for (size_t e = blockIdx.x * (size_t)256 + threadIdx.x; e < len; e += (size_t)gridDim.x * 256) {
+        // the loads of eight partials are issued together; the sum runs over
+        // p in order
         double s = 0.0;
-        for (int p = 0; p < S; ++p) s += (double)Ypart[(size_t)p * len + e];
+        int p = 0;
+        for (; p + 8 <= S; p += 8) {
+            double t[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t[q] = (double)Ypart[(size_t)(p + q) * len + e];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s += t[q];
+        }
+        for (; p < S; ++p) s += (double)Ypart[(size_t)p * len + e];
         Y0[e] = (T)s;
     }
 }
@@ -447,8 +457,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ 
 __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__restrict__ cq,
                                                  unsigned *__restrict__ flag)
 {
-    __shared__ double M[64 * 65], X[64 * 65], R1s[64 * 65], part[4][64], rinv[64];
-    __shared__ int bad;
+    __shared__ double M[64 * 65], X[64 * 65], R1s[64 * 65], part[4];
+    __shared__ __attribute__((aligned(16))) double buf[320];
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     if (pass == 2 && *flag) return;
     const size_t BB = 64 * 64;
@@ -466,28 +476,21 @@ __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__rest
             if (in) emax = fmax(emax, fabs(gv - ((tx == j) ? 1.0 : 0.0)));
         }
     }
-    if (tid == 0) bad = 0;
-    if (pass == 2) part[ty][tx] = wave_max(emax);
+    if (pass == 2) {
+        const double wm = wave_max(emax);
+        if (tx == 0) part[ty] = wm;
+    }
     __syncthreads();
     bool first_order = false;
-    if (pass == 2) {
-        const double e = fmax(fmax(part[0][0], part[1][0]), fmax(part[2][0], part[3][0]));
-        first_order = e <= 1e-8;
-    }
+    if (pass == 2) first_order = fmax(fmax(part[0], part[1]), fmax(part[2], part[3])) <= 1e-8;
     if (first_order) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int c = ty + 4 * q;
             const double e = M[tx * 65 + c] - ((tx == c) ? 1.0 : 0.0);
             const double f = (tx == c) ? 0.5 * e : ((tx < c) ? e : 0.0);
-            X[tx * 65 + c] = ((tx == c) ? 1.0 : 0.0) - f;   // R2^{-1}
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int c = ty + 4 * q;
-            const double e = M[tx * 65 + c] - ((tx == c) ? 1.0 : 0.0);
-            M[tx * 65 + c] = ((tx == c) ? 1.0 + 0.5 * e : ((tx < c) ? e : 0.0));   // R2 (own elements)
+            X[tx * 65 + c] = ((tx == c) ? 1.0 : 0.0) - f;                                 // R2^{-1}
+            M[tx * 65 + c] = ((tx == c) ? 1.0 + 0.5 * e : ((tx < c) ? e : 0.0));         // R2
         }
         __syncthreads();
     } else {
@@ -495,35 +498,28 @@ __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__rest
 #pragma unroll
         for (int i = 0; i < 64; ++i) dmax = fmax(dmax, (i < B) ? M[i * 65 + i] : 0.0);
         const double lo = (pass == 1) ? 1e-13 * dmax : 0.5, hi = (pass == 1) ? 2.0 * dmax : 2.0;
-        const bool ok = cholesky64(M, B, false, lo, hi, &bad);
-        __syncthreads();
-        if (!ok || bad) {
+        if (!chol_inv64(M, X, B, false, lo, hi, buf)) {
             if (tid == 0) *flag = 1u;
             return;
         }
-        tri_inv_upper(M, X, B, part, rinv);
     }
     double *Ro = cq + ((pass == 1) ? CQ_R1 : CQ_R) * BB;
     double *Ri = cq + ((pass == 1) ? CQ_R1INV : CQ_R2INV) * BB;
-    // pass 2: (R2 R1)[r][c] = sum_{r <= u <= c} R2[r][u] R1[u][c]
-    double acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    if (pass == 2) {
-#pragma unroll 8
-        for (int u = 0; u < 64; ++u) {
-            const double a = (u >= tx) ? M[tx * 65 + u] : 0.0;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q] += R1s[u * 65 + ty + 4 * q] * a;
-        }
-    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
-        if (tx < B && j < B) {
-            Ri[(size_t)j * B + tx] = (tx <= j) ? X[tx * 65 + j] : 0.0;
-            Ro[(size_t)j * B + tx] = (tx <= j) ? ((pass == 1) ? M[tx * 65 + j] : acc[q]) : 0.0;
-        }
+        if (tx < B && j < B) Ri[(size_t)j * B + tx] = X[tx * 65 + j];
+    }
+    if (pass == 2) {   // R = R2 R1 on the MFMA, into X once R2^{-1} is stored
+        __syncthreads();
+        mm64<false>(M, R1s, X);
+        __syncthreads();
+    }
+    const double *Rs = (pass == 1) ? M : X;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int j = ty + 4 * q;
+        if (tx < B && j < B) Ro[(size_t)j * B + tx] = (tx <= j) ? Rs[tx * 65 + j] : 0.0;
     }
     if (pass == 1 && tid == 0) *flag = 0u;
 }
@@ -531,23 +527,17 @@ __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__rest
 // Householder reconstruction from the orthonormal Q (in Vd, m x B, ld m):
 // writes V's top block L into Vd, T into Tf (column-major), tau = diag(T),
 // R_h = S R into the panel's top block of W (upper triangle), U^{-1} into
-// cq[CQ_UINV].  Nothing is done when the flag is set.  Two workgroups: both
-// factor the top block (the same deterministic steps, so the same L, U and
-// S), then workgroup 1 inverts U and writes L, U^{-1} and R_h while
-// workgroup 0 forms T and tau.  L overwrites the input block, so workgroup 0
-// sets *hand once it holds its copy of the input and workgroup 1 waits for
-// that (bounded; code 4 in *err) before writing, then clears *hand for the
-// next launch.  The waiting workgroup is the later one: workgroups start in
-// order, so the one it waits for is already running even when the device is
-// shared with other work.
+// cq[CQ_UINV].  Nothing is done when the flag is set.  One workgroup: the
+// signed LU of the top block with L^{-1} and U^{-1} in one elimination pass,
+// then T = -U S L^{-T} on the MFMA.  The input block is read into LDS before
+// L overwrites it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, int B, T *__restrict__ Wp,
                                                     int ldw, double *__restrict__ cq, double *__restrict__ Tf,
-                                                    double *__restrict__ tau, const unsigned *__restrict__ flag,
-                                                    unsigned *hand, unsigned *err)
+                                                    double *__restrict__ tau, const unsigned *__restrict__ flag)
 {
-    __shared__ double M[64 * 65], X[64 * 65], Ts[64 * 65], sgn[64], part[4][64], rinv[64];
-    __shared__ int bad;
+    __shared__ double M[64 * 65], Xu[64 * 65], Yl[64 * 65], sgn[64];
+    __shared__ __attribute__((aligned(16))) double buf[1024];
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     if (*flag) return;
     const size_t BB = 64 * 64;
@@ -555,62 +545,37 @@ __global__ __launch_bounds__(256) void k_hh_rebuild(T *__restrict__ Vd, int m, i
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
         M[tx * 65 + j] = (tx < B && j < B) ? (double)Vd[(size_t)j * m + tx] : 0.0;
-        Ts[tx * 65 + j] = 0.0;
     }
-    if (tid < 64) sgn[tid] = 0.0;
     __syncthreads();
-    if (blockIdx.x == 0 && tid == 0) st_relaxed(hand, 1u);   // the input is in LDS
-    lu_signed64(M, B, sgn);
+    lu_signed_inv64(M, Xu, Yl, B, sgn, buf);
     const double *R = cq + CQ_R * BB;
-    if (blockIdx.x == 1) {
-        tri_inv_upper(M, X, B, part, rinv);        // X = U^{-1}
-        if (tid == 0) {
-            unsigned spins = 0;
-            while (ld_relaxed(hand) == 0u) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > SKEW_SPIN_LIMIT) {
-                    atomicOr(err, 4u);
-                    break;
-                }
-            }
-            st_relaxed(hand, 0u);
-        }
-        __syncthreads();
-        double *Ui = cq + CQ_UINV * BB;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int c = ty + 4 * q, r = tx;
-            if (r < B && c < B) {
-                Vd[(size_t)c * m + r] = (T)((r > c) ? M[r * 65 + c] : ((r == c) ? 1.0 : 0.0));
-                Ui[(size_t)c * B + r] = (r <= c) ? X[r * 65 + c] : 0.0;
-                if (r <= c) Wp[(size_t)c * ldw + r] = (T)(sgn[r] * R[(size_t)c * B + r]);
-            }
-        }
-        return;
-    }
-    // T = -U S L^{-T} by columns: T[r][c] = -u_rc s_c - sum_{r <= k < c} T[r][k] l_ck
-    for (int c = 0; c < B; ++c) {
-        // Ts is zero below the diagonal and in columns >= c: no masks
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; q += 2) {
-            const int k = ty + 4 * q;
-            s0 = fma(Ts[tx * 65 + k], M[c * 65 + k], s0);
-            s1 = fma(Ts[tx * 65 + k + 4], M[c * 65 + k + 4], s1);
-        }
-        part[ty][tx] = s0 + s1;
-        __syncthreads();
-        if (ty == 0 && tx <= c)
-            Ts[tx * 65 + c] = -M[tx * 65 + c] * sgn[c] - (part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx]);
-        __syncthreads();
-    }
-    // outputs of workgroup 0: T, tau
+    double *Ui = cq + CQ_UINV * BB;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int c = ty + 4 * q, r = tx;
         if (r < B && c < B) {
-            Tf[(size_t)c * B + r] = (r <= c) ? Ts[r * 65 + c] : 0.0;
-            if (r == c) tau[r] = Ts[r * 65 + r];
+            Vd[(size_t)c * m + r] = (T)((r > c) ? M[r * 65 + c] : ((r == c) ? 1.0 : 0.0));
+            Ui[(size_t)c * B + r] = Xu[r * 65 + c];
+            if (r <= c) Wp[(size_t)c * ldw + r] = (T)(sgn[r] * R[(size_t)c * B + r]);
+        }
+    }
+    __syncthreads();
+    // U S into Xu, L^{-T} into M (each thread rewrites the elements it read)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int c = ty + 4 * q, r = tx;
+        Xu[r * 65 + c] = (r <= c && c < B) ? M[r * 65 + c] * sgn[c] : 0.0;   // sgn[c >= B] is not set
+        M[r * 65 + c] = Yl[c * 65 + r];
+    }
+    __syncthreads();
+    mm64<false>(Xu, M, Yl);   // Yl = U S L^{-T}
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int c = ty + 4 * q, r = tx;
+        if (r < B && c < B) {
+            Tf[(size_t)c * B + r] = (r <= c) ? -Yl[r * 65 + c] : 0.0;
+            if (r == c) tau[r] = -Yl[r * 65 + r];
         }
     }
 }
@@ -697,7 +662,7 @@ int symm_splits(int m)
     return S;
 }
 int symm_kchunk(int m, int S) { return (int)(cdiv(cdiv(m, S), 16) * 16); }
-int gram_chunk_rows() { return 512; }
+int gram_chunk_rows() { return 256; }
 
 template <typename T>
 void launch_stage1_w(T *W, int ldw, int r0, int m, int B, const T *Vd, const double *Tf, T *Ypart,
@@ -770,14 +735,14 @@ void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st)
 }
 template <typename T>
 void launch_hh_rebuild(T *Vd, int m, int B, T *Wp, int ldw, double *cq, double *Tf, double *tau,
-                       const unsigned *flag, unsigned *hand, unsigned *err, hipStream_t st)
+                       const unsigned *flag, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_hh_rebuild<T>, dim3(2), dim3(256), 0, st, Vd, m, B, Wp, ldw, cq, Tf, tau, flag, hand, err);
+    hipLaunchKernelGGL(k_hh_rebuild<T>, dim3(1), dim3(256), 0, st, Vd, m, B, Wp, ldw, cq, Tf, tau, flag);
 }
 template void launch_hh_rebuild<double>(double *, int, int, double *, int, double *, double *, double *,
-                                        const unsigned *, unsigned *, unsigned *, hipStream_t);
+                                        const unsigned *, hipStream_t);
 template void launch_hh_rebuild<float>(float *, int, int, float *, int, double *, double *, double *,
-                                       const unsigned *, unsigned *, unsigned *, hipStream_t);
+                                       const unsigned *, hipStream_t);
 size_t cholqr_scratch_doubles() { return (size_t)6 * 64 * 64; }
 
 template hipError_t launch_panel_qr<double>(double *, int, int, int, int, int, double *, double *, double *,

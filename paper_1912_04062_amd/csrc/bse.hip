@@ -52,10 +52,9 @@ __global__ void k_bse_build_m(const double *__restrict__ Ar, const double *__res
 __global__ __launch_bounds__(256) void k_chol_diag(double *__restrict__ M, int ldm, int j0, int nb,
                                                    double *__restrict__ Rinv, unsigned *flags)
 {
-    __shared__ double G[64 * 65], X[64 * 65], part[4][64], rinv[64];
-    __shared__ int bad;
+    __shared__ double G[64 * 65], X[64 * 65];
+    __shared__ __attribute__((aligned(16))) double buf[320];
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-    if (tid == 0) bad = 0;
     if (*flags & 4u) return;                  // an earlier block already failed
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -68,12 +67,10 @@ __global__ __launch_bounds__(256) void k_chol_diag(double *__restrict__ M, int l
         G[tx * 65 + c] = v;
     }
     __syncthreads();
-    if (!cholesky64(G, nb, false, 0.0, 1.7976931348623157e308, &bad)) {
+    if (!chol_inv64(G, X, nb, false, 0.0, 1.7976931348623157e308, buf)) {
         if (tid == 0) atomicOr(flags, 4u);
         return;
     }
-    __syncthreads();
-    tri_inv_upper(G, X, nb, part, rinv);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int c = ty + 4 * q;

@@ -180,6 +180,17 @@ __device__ __forceinline__ void sum_partials_2d(const double *__restrict__ P, in
     }
 }
 
+// 1/d for a normal d: the hardware estimate refined by two Newton steps
+// r <- r (2 - d r), each of which squares the relative error, so the result
+// is within an ulp or two of the rounded quotient.
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
 // Wavefront maximum (64 lanes) via cross-lane shuffles.
 __device__ __forceinline__ double wave_max(double v)
 {

@@ -25,7 +25,7 @@ void launch_gram_reduce(const double *Gp, int np, int BB, double *G, hipStream_t
 void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st);
 template <typename T>
 void launch_hh_rebuild(T *Vd, int m, int B, T *Wp, int ldw, double *cq, double *Tf, double *tau,
-                       const unsigned *flag, unsigned *hand, unsigned *err, hipStream_t st);
+                       const unsigned *flag, hipStream_t st);
 int symm_splits(int m);
 int symm_kchunk(int m, int S);
 int gram_chunk_rows();

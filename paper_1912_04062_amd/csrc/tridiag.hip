@@ -66,18 +66,6 @@ __global__ void k_alpha2(const double *__restrict__ alpha, int n, double *__rest
     }
 }
 
-// 1/d for a normal d (|d| >= pivmin): the hardware estimate refined by two
-// Newton steps r <- r (2 - d r), each of which squares the relative error,
-// so the result is within an ulp or two of the rounded quotient -- the
-// small relative perturbation of each pivot that the Sturm count tolerates.
-__device__ __forceinline__ double recip(double d)
-{
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(r, fma(-d, r, 1.0), r);
-    r = fma(r, fma(-d, r, 1.0), r);
-    return r;
-}
-
 // 256 threads = 16 eigenvalues x 16 shifts.  Eigenvalue index first + e.
 __global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, int n, int first, int count,
                                                 const double *__restrict__ stats, int rounds,
@@ -416,8 +404,8 @@ __global__ void k_transpose_in(const double *__restrict__ Q, int ldq, int n, int
 __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp, int nparts, int NB,
                                                   double *__restrict__ Rinv)
 {
-    __shared__ double G[64 * 65], X[64 * 65], part[4][64], rinv[64];
-    __shared__ int bad;
+    __shared__ double G[64 * 65], X[64 * 65], part[4][64];
+    __shared__ __attribute__((aligned(16))) double buf[320];
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     double emax = 0.0;
     {
@@ -445,8 +433,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp,
         return;
     }
     __syncthreads();
-    cholesky64(G, NB, true, 0.0, 0.0, &bad);
-    tri_inv_upper(G, X, NB, part, rinv);
+    chol_inv64(G, X, NB, true, 0.0, 0.0, buf);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
