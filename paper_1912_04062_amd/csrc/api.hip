@@ -188,7 +188,7 @@ Layout plan_layout(const Plan &p)
     const size_t wmax = std::max((size_t)p.nev, (size_t)ORTH_NB);
     L.Pp = take(sizeof(double) * tn_parts_max() * wmax * ORTH_NB);
     L.P = take(sizeof(double) * wmax * ORTH_NB);
-    L.Gp2 = take(sizeof(double) * tn_parts_max() * ORTH_NB * ORTH_NB);
+    L.Gp2 = take(sizeof(double) * std::max(tn_parts_max(), cholqr_max_splits()) * ORTH_NB * ORTH_NB);
     L.Rinv = take(sizeof(double) * ORTH_NB * ORTH_NB);
     L.Tmp = take(sizeof(double) * n * ORTH_NB);
     L.ctl = take(sizeof(unsigned) * (64 + n));
@@ -629,8 +629,12 @@ int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, 
             skew::launch_gram_reduce(ptr<double>(h, L.Pp), S, wl * nb, ptr<double>(h, L.P), st);
             skew::launch_gemm_nn<double>(Qw, ldq, ptr<double>(h, L.P), 1, n, nb, wl, Qb, ldq, -1.0, 1, st);
         }
-        int S = skew::launch_gemm_tn_part<double>(Qb, ldq, Qb, ldq, nb, nb, n, ptr<double>(h, L.Gp2), st);
-        skew::launch_chol_inv(ptr<double>(h, L.Gp2), S, nb, ptr<double>(h, L.Rinv), st);
+        // the block's Gram matrix: short row chunks (a short chain of K-chunks
+        // per workgroup), their partials summed in parallel (into P, free here)
+        int S = skew::launch_gemm_tn_part<double>(Qb, ldq, Qb, ldq, nb, nb, n, ptr<double>(h, L.Gp2), st,
+                                                  cholqr_splits(n));
+        skew::launch_gram_reduce(ptr<double>(h, L.Gp2), S, nb * nb, ptr<double>(h, L.P), st);
+        skew::launch_chol_inv(ptr<double>(h, L.P), 1, nb, ptr<double>(h, L.Rinv), st);
         skew::launch_gemm_nn<double>(Qb, ldq, ptr<double>(h, L.Rinv), 1, n, nb, nb, ptr<double>(h, L.Tmp), n, 1.0, 0,
                                      st);
         skew::launch_copy_cols<double>(ptr<double>(h, L.Tmp), n, Qb, ldq, n, nb, st);

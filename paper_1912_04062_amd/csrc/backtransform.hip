@@ -606,7 +606,7 @@ __global__ __launch_bounds__(256) GEMM_OCC2 void k_bt1_w(
     auto fb = [=](int j, int row) -> T { return (row < ke && j < ncols) ? Z[(size_t)j * ldz + row] : T(0); };
     gemm::Acc<T, KK, TN> acc;
     acc.zero();
-    gemm::kloop<T, KK, TN, true, true>(fa, fb, 0, n0, kb, ke, smem, acc);
+    gemm::kloop_db<T, KK, TN, true, true>(fa, fb, 0, n0, kb, ke, smem, acc);
     double *W = Wp + (size_t)s * KK * ncols;
     gemm::epilogue<T, KK, TN>(acc, smem, [=](int i, int j, T v) {
         if (n0 + j < ncols) W[(size_t)(n0 + j) * KK + i] = (double)v;
@@ -910,9 +910,14 @@ void launch_gemm_nn(const T *A, int lda, const double *Bpart, int S, int M, int 
         dim3 grid(cdiv(M, 128), cdiv(N, 128));
         hipLaunchKernelGGL((k_gemm_nn<T, 128, 128>), grid, dim3(256), (gemm::smem_bytes<T, 128, 128>()), st, A, lda,
                            Bpart, S, M, N, K, C, ldc, alpha, beta);
-    } else {
+    } else if ((size_t)cdiv(M, 64) * cdiv(N, 64) >= 512) {
         dim3 grid(cdiv(M, 64), cdiv(N, 64));
         hipLaunchKernelGGL((k_gemm_nn<T, 64, 64>), grid, dim3(256), (gemm::smem_bytes<T, 64, 64>()), st, A, lda, Bpart,
+                           S, M, N, K, C, ldc, alpha, beta);
+    } else {
+        // thin products (n x 64 blocks): 32-row tiles, two workgroups per CU
+        dim3 grid(cdiv(M, 32), cdiv(N, 64));
+        hipLaunchKernelGGL((k_gemm_nn<T, 32, 64>), grid, dim3(256), (gemm::smem_bytes<T, 32, 64>()), st, A, lda, Bpart,
                            S, M, N, K, C, ldc, alpha, beta);
     }
 }
@@ -980,7 +985,15 @@ static void bt1_block(T *Z, int ldz, int m, int ncols, MergedV<T> V, const doubl
     int S = bt1_splits(m, ncols);
     const int kc = (int)(cdiv(cdiv(m, S), 16) * 16);
     S = (int)cdiv(m, kc);
-    hipLaunchKernelGGL((k_bt1_w<T, KK>), dim3(cdiv(ncols, 128), S), dim3(256), (gemm::smem_bytes<T, KK, 128>()), st,
+    constexpr size_t shw = gemm::smem_bytes_db<T, KK, 128>();
+    if constexpr (shw > 65536) {   // dynamic LDS above 64 KB needs the kernel attribute
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void *)k_bt1_w<T, KK>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shw);
+            attr = true;
+        }
+    }
+    hipLaunchKernelGGL((k_bt1_w<T, KK>), dim3(cdiv(ncols, 128), S), dim3(256), shw, st,
                        (const T *)Z, ldz, ncols, V, kc, Wp);
     hipLaunchKernelGGL((k_bt1_t<T, KK>), dim3(cdiv(ncols, 64)), dim3(256), (gemm::smem_bytes<T, KK, 64>()), st, Tm,
                        (const double *)Wp, S, ncols, W2);

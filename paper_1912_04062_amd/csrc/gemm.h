@@ -180,6 +180,45 @@ __device__ __forceinline__ void kloop(const FA &fa, const FB &fb, int m0, int n0
     }
 }
 
+// The same K loop with the operand chunks alternating between two LDS
+// buffers: chunk i + 1 is stored into the other buffer after the MFMAs of
+// chunk i, and one workgroup barrier per chunk separates the two (a buffer is
+// rewritten only after every wave has passed the barrier that ends the chunk
+// that read it).  It needs smem_bytes_db<T, TM, TN>() bytes, which costs
+// occupancy where LDS limits it; kernels whose registers already limit them
+// to two workgroups per CU gain from the saved barrier.
+template <typename T, int TM, int TN, bool AKC, bool BKC, class FA, class FB>
+__device__ __forceinline__ void kloop_db(const FA &fa, const FB &fb, int m0, int n0, int kb, int ke,
+                                         T *smem, Acc<T, TM, TN> &acc)
+{
+    constexpr int HALF = TK * lds_ld<TM>() + TK * lds_ld<TN>();
+    if (kb >= ke) return;
+    Frag<T, TM> ra;
+    Frag<T, TN> rb;
+    gload<T, TM, AKC>(ra, fa, m0, kb);
+    gload<T, TN, BKC>(rb, fb, n0, kb);
+    lstore<T, TM, AKC>(smem, ra);
+    lstore<T, TN, BKC>(smem + TK * lds_ld<TM>(), rb);
+    __syncthreads();
+    int q = 0;
+    for (int k0 = kb; k0 < ke; k0 += TK) {
+        T *As = smem + q * HALF;
+        const bool more = k0 + TK < ke;
+        if (more) {
+            gload<T, TM, AKC>(ra, fa, m0, k0 + TK);
+            gload<T, TN, BKC>(rb, fb, n0, k0 + TK);
+        }
+        mma_chunk<T, TM, TN>(As, As + TK * lds_ld<TM>(), acc);
+        if (more) {
+            T *An = smem + (q ^ 1) * HALF;
+            lstore<T, TM, AKC>(An, ra);
+            lstore<T, TN, BKC>(An + TK * lds_ld<TM>(), rb);
+        }
+        __syncthreads();
+        q ^= 1;
+    }
+}
+
 // K loop whose A operand is a skew matrix read from its strict lower
 // triangle: chunks left of the tile's rows come from the lower triangle
 // (x-contiguous), chunks right of them from the transposed lower triangle
@@ -261,6 +300,13 @@ __device__ __forceinline__ void epilogue_rmw(const Acc<T, TM, TN> &acc, T *smem,
 template <typename T, int TM, int TN> __host__ __device__ constexpr size_t smem_bytes()
 {
     size_t ops = (size_t)(TK * (TM + 1) + TK * (TN + 1));
+    size_t epi = (size_t)32 * (TM + 1);
+    return sizeof(T) * (ops > epi ? ops : epi);
+}
+
+template <typename T, int TM, int TN> __host__ __device__ constexpr size_t smem_bytes_db()
+{
+    size_t ops = (size_t)2 * (TK * (TM + 1) + TK * (TN + 1));
     size_t epi = (size_t)32 * (TM + 1);
     return sizeof(T) * (ops > epi ? ops : epi);
 }
