@@ -244,6 +244,16 @@ int auto_band(int n)
 // them per size class only where they win.)
 constexpr int HH_PANEL_NMAX = 0;
 
+// Fixed part of the Gram-Schmidt windows (beyond it a window extends over a
+// cluster, see plan_windows): up to 2048 vectors every vector, else the 256
+// before the block.  Inverse iteration leaves a component of size about
+// eps ||T|| / gap along the vector of an eigenvalue a gap away; 256 vectors
+// span about 256 / nev of the spectrum (gaps of several percent of ||T|| for
+// spread spectra), so the components left behind sum to orders of magnitude
+// below the orthogonality tolerance, and closer eigenvalues are covered by
+// the cluster rule.
+int orth_window_for(int nev) { return nev <= 2048 ? nev : 256; }
+
 Plan make_plan(int n, int nev, int b, int prec, int panel = SKEW_EVD_PANEL_AUTO, bool onestage = false,
                bool herm = false)
 {
@@ -256,7 +266,7 @@ Plan make_plan(int n, int nev, int b, int prec, int panel = SKEW_EVD_PANEL_AUTO,
         p.nev = nev;
         p.b = p.nb2 = 64;
         p.npanels = n >= 2 ? (n - 1 + 63) / 64 : 0;
-        p.orth_window = nev <= 2048 ? nev : 1024;
+        p.orth_window = orth_window_for(nev);
         return p;
     }
     p.hh_panels = panel == SKEW_EVD_PANEL_HOUSEHOLDER || (panel == SKEW_EVD_PANEL_AUTO && n <= HH_PANEL_NMAX);
@@ -269,7 +279,7 @@ Plan make_plan(int n, int nev, int b, int prec, int panel = SKEW_EVD_PANEL_AUTO,
     for (int c0 = 0; c0 + p.b < n - 1; c0 += p.b) ++p.npanels;
     p.nsig = n > 2 ? (n - 2 + p.nb2 - 1) / p.nb2 : 0;
     p.ngroups = skew::chase_ngroups(n, p.b, p.nb2, nullptr);
-    p.orth_window = nev <= 2048 ? nev : 1024;
+    p.orth_window = orth_window_for(nev);
     return p;
 }
 
