@@ -779,6 +779,9 @@ int stage_bt_herm(skew_evd_handle h, const Plan &p, const Layout &L)
 // is reported as not converged.
 constexpr double INVIT_CTOL = 1e-12;
 
+int tridiag_finish(skew_evd_handle h, const Plan &p, const Layout &L, const double *alpha, int nev, double *lam,
+                   double *Q, int ldq, const double *diag);
+
 // early_t: start the T factors of the stage-2 groups on the second stream
 // once the bisection (which fills the device) is queued, so that they run
 // beside the inverse iteration.
@@ -802,7 +805,22 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
                                  ptr<unsigned char>(h, L.Sw), ptr<double>(h, L.Yiv), ptr<double>(h, L.ivfac), Q,
                                  ldq, ctol, ptr<unsigned>(h, L.ctl) + CTL_ERR, st, diag);
     HCHK(hipGetLastError());
-    rc = plan_windows(h, p, nev);
+    rc = tridiag_finish(h, p, L, alpha, nev, lam, Q, ldq, diag);
+    if (rc) return rc;
+    HCHK(kt_end(h, SKEW_EVD_K_TRIDIAG));
+    HCHK(ev_record(h, 4));
+    return SKEW_EVD_OK;
+}
+
+// After the eigenvalues (lam) and the inverse-iteration vectors (Q): the
+// Gram-Schmidt windows and pass, then the degenerate clusters (polished here,
+// or flagged on the device in the batched form).
+int tridiag_finish(skew_evd_handle h, const Plan &p, const Layout &L, const double *alpha, int nev, double *lam,
+                   double *Q, int ldq, const double *diag)
+{
+    hipStream_t st = h->stream;
+    const int n = p.n;
+    int rc = plan_windows(h, p, nev);
     if (rc) return rc;
     rc = orthogonalize(h, p, L, Q, ldq, n, nev);
     if (rc) return rc;
@@ -825,8 +843,6 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
         skew::launch_degenerate_check(lam, nev, ptr<double>(h, L.stats), DEGEN_TOL, ptr<unsigned>(h, L.ctl) + CTL_FLAGS,
                                       st);
     }
-    HCHK(kt_end(h, SKEW_EVD_K_TRIDIAG));
-    HCHK(ev_record(h, 4));
     return SKEW_EVD_OK;
 }
 
@@ -1540,10 +1556,10 @@ int batch_part_c(skew_evd_handle v, const BatchItem &it, double *lambda, double 
     const Layout &L = it.L;
     const int n = p.n, nev = p.nev;
     hipStream_t st = v->stream;
-    skew::launch_alpha(ptr<double>(v, L.ab), 2 * p.b + 1, n, ptr<double>(v, L.alpha), st);
-    if (n == 1) skew::launch_fill32(ptr<double>(v, L.alpha), 0u, 2, st);
-    int rc = stage_tridiag(v, p, L, ptr<double>(v, L.alpha), nev, ptr<double>(v, L.lam), ptr<double>(v, L.Qd), n,
-                           false);
+    // alpha, the eigenvalues and the inverse-iteration vectors come from the
+    // batched tridiagonal launches (tri_prob)
+    int rc = tridiag_finish(v, p, L, ptr<double>(v, L.alpha), nev, ptr<double>(v, L.lam), ptr<double>(v, L.Qd), n,
+                            nullptr);
     if (rc) return rc;
     rc = stage_backtransform<double>(v, p, L, false);
     if (rc) return rc;
@@ -1553,6 +1569,39 @@ int batch_part_c(skew_evd_handle v, const BatchItem &it, double *lambda, double 
     HCHK(hipMemcpyAsync(Z_im, Z + (size_t)nev * n, sizeof(double) * n * nev, hipMemcpyDeviceToDevice, st));
     HCHK(hipMemcpyAsync(stat, ptr<unsigned>(v, L.ctl), sizeof(unsigned) * 2, hipMemcpyDeviceToDevice, st));
     return SKEW_EVD_OK;
+}
+
+// The problem's entry of the batched tridiagonal launches (its workspace
+// slice starts at w).
+skew::TriProb tri_prob(char *w, const BatchItem &it)
+{
+    const Plan &p = it.p;
+    const Layout &L = it.L;
+    skew::TriProb t{};
+    t.ab = (const double *)(w + L.ab);
+    t.alpha = (double *)(w + L.alpha);
+    t.a2 = (double *)(w + L.a2);
+    t.stats = (double *)(w + L.stats);
+    t.w = (double *)(w + L.lam);
+    t.U0 = (double *)(w + L.U0);
+    t.U1 = (double *)(w + L.U1);
+    t.U2 = (double *)(w + L.U2);
+    t.Lm = (double *)(w + L.Lm);
+    t.Y = (double *)(w + L.Yiv);
+    t.fac = (double *)(w + L.ivfac);
+    t.Q = (double *)(w + L.Qd);
+    t.Sw = (unsigned char *)(w + L.Sw);
+    t.err = (unsigned *)(w + L.ctl) + CTL_ERR;
+    t.diag = nullptr;
+    t.shifts = nullptr;
+    t.ctol = INVIT_CTOL;
+    t.ldab = 2 * p.b + 1;
+    t.n = p.n;
+    t.first = p.n / 2;
+    t.nev = p.nev;
+    t.ldq = p.n;
+    t.iters = 3;
+    return t;
 }
 
 int ensure_streams(skew_evd_handle h, int S)
@@ -1612,8 +1661,12 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
     const int M = std::min(cnt, CHASE_LANES);
     const size_t probs_off = off;
     off += al(sizeof(skew::ChaseProb) * cnt);
+    const size_t tri_off = off;
+    off += al(sizeof(skew::TriProb) * cnt);
     const size_t lanes_off = off;
     off += al(sizeof(int) * (M + 1 + 2 * cnt));
+    const size_t pre_off = off;
+    off += al(sizeof(int) * 3 * (cnt + 1));
     const size_t stat_off = off;
     off += al(sizeof(unsigned) * (2 * cnt + 2));
     int rc = ensure_ws(h, off, wslimit);
@@ -1637,8 +1690,10 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
         lane[l].push_back(k);
         lload[l] += std::max(it[k].p.n - 2, 0);
     }
-    // host images of the chase descriptors, then one copy to the device
-    const size_t hbytes = sizeof(skew::ChaseProb) * cnt + sizeof(int) * (M + 1 + 2 * cnt) +
+    // host images of the chase and tridiagonal descriptors, then one copy
+    // each to the device
+    const size_t hbytes = sizeof(skew::ChaseProb) * cnt + sizeof(skew::TriProb) * cnt +
+                          sizeof(int) * (M + 1 + 2 * cnt) + sizeof(int) * 3 * (cnt + 1) +
                           sizeof(unsigned) * (2 * cnt + 2);
     if (hbytes > h->bhost_cap) {
         if (h->bhost) {
@@ -1653,8 +1708,10 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
         ++h->bhost_gen;
     }
     skew::ChaseProb *hp = (skew::ChaseProb *)h->bhost;
-    int *hl = (int *)(hp + cnt);
-    unsigned *hs = (unsigned *)(hl + M + 1 + 2 * cnt);
+    skew::TriProb *ht = (skew::TriProb *)(hp + cnt);
+    int *hl = (int *)(ht + cnt);
+    int *hpre = hl + M + 1 + 2 * cnt;
+    unsigned *hs = (unsigned *)(hpre + 3 * (cnt + 1));
     int maxlen = 0, nitem = 0;
     for (int l = 0; l < M; ++l) {
         hl[l] = nitem;
@@ -1676,9 +1733,26 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
         hp[k] = skew::ChaseProb{(double *)(w + L.ab), (double *)(w + L.V2), (double *)(w + L.tau2),
                                 (const int *)(w + L.goff), ctl + CTL_PROGRESS, ctl + CTL_ERR, 2 * p.b + 1, p.n,
                                 p.b, p.nb2};
+        ht[k] = tri_prob(w, it[k]);
+    }
+    // workgroups per problem of the batched bisection, inverse iteration and
+    // transposition: prefix tables
+    int tot[3] = {0, 0, 0};
+    for (int t = 0; t < 3; ++t) {
+        int *pt = hpre + t * (cnt + 1);
+        pt[0] = 0;
+        for (int k = 0; k < cnt; ++k) {
+            const int nn = it[k].p.n, ne = it[k].p.nev;
+            const int gk = (t == 0) ? skew::tri_bisect_groups(ne)
+                                    : ((t == 1) ? skew::tri_invit_groups(ne) : skew::tri_transpose_groups(nn, ne));
+            pt[k + 1] = pt[k] + gk;
+        }
+        tot[t] = pt[cnt];
     }
     skew::ChaseProb *dprobs = (skew::ChaseProb *)(h->ws + probs_off);
+    skew::TriProb *dtri = (skew::TriProb *)(h->ws + tri_off);
     int *dlanes = (int *)(h->ws + lanes_off);
+    int *dpre = (int *)(h->ws + pre_off);
     unsigned *dstat = (unsigned *)(h->ws + stat_off);
     // The launch sequence depends on nothing but this key.  Its first call
     // captures the sequence as a HIP graph (on bstream, which can be
@@ -1724,7 +1798,9 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
         };
         auto enqueue = [&]() -> int {
             HCHK(hipMemcpyAsync(dprobs, hp, sizeof(skew::ChaseProb) * cnt, hipMemcpyHostToDevice, ms));
+            HCHK(hipMemcpyAsync(dtri, ht, sizeof(skew::TriProb) * cnt, hipMemcpyHostToDevice, ms));
             HCHK(hipMemcpyAsync(dlanes, hl, sizeof(int) * (M + 1 + 2 * cnt), hipMemcpyHostToDevice, ms));
+            HCHK(hipMemcpyAsync(dpre, hpre, sizeof(int) * 3 * (cnt + 1), hipMemcpyHostToDevice, ms));
             skew::launch_fill32(dstat, 0u, 2 * (size_t)cnt + 2, ms);
             int r2 = fork_streams(h, ms, S);
             if (r2) return r2;
@@ -1734,6 +1810,8 @@ int batched_together(skew_evd_handle h, const std::vector<int> &ids, const int *
             if (r2) return r2;
             const int G = std::max(1, std::min(skew::chase_max_workgroups(), 8 * M));
             HCHK(skew::launch_chase_batched(dprobs, dlanes, M, maxlen, G, dstat + 2 * cnt, ms));
+            skew::launch_tridiag_batched(dtri, dpre, cnt, tot, ms);
+            HCHK(hipGetLastError());
             r2 = fork_streams(h, ms, S);
             if (r2) return r2;
             run_parts(false);

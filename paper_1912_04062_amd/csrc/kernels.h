@@ -72,6 +72,29 @@ void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w
 void launch_tridiag_polish(const double *alpha, int n, int m, const double *w, const double *shifts,
                            const double *stats, double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw,
                            double *Y, double *fac, double *Q, int ldq, hipStream_t st, const double *diag = nullptr);
+// One tridiagonal problem of the batched eigenvalue and eigenvector launches
+// (device pointers into the problem's workspace; ab: its band, from which
+// alpha is extracted first).  first: index of the first eigenvalue (n / 2),
+// nev: eigenpairs, iters: inverse-iteration steps, ctol: its residual test.
+struct TriProb {
+    const double *ab;
+    double *alpha, *a2, *stats, *w;
+    double *U0, *U1, *U2, *Lm, *Y, *fac, *Q;
+    unsigned char *Sw;
+    unsigned *err;
+    const double *diag, *shifts;
+    double ctol;
+    int ldab, n, first, nev, ldq, iters;
+};
+// Workgroups per problem of the batched launches (prefix tables over the
+// problems, cnt + 1 entries each, in this order in `pre`).
+int tri_bisect_groups(int nev);
+int tri_invit_groups(int nev);
+int tri_transpose_groups(int n, int nev);
+// alpha from the band, alpha^2 and the norms, eigenvalues, eigenvectors (with
+// the odd-order null vector) into each problem's Q: one launch per kernel for
+// all cnt problems; tot[t] = pre table t's last entry
+void launch_tridiag_batched(const TriProb *probs, const int *pre, int cnt, const int tot[3], hipStream_t st);
 // sets *flag when two consecutive values of w[0..m) are closer than tol * stats[0]
 void launch_degenerate_check(const double *w, int m, const double *stats, double tol, unsigned *flag,
                              hipStream_t st);

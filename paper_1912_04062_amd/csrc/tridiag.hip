@@ -31,11 +31,51 @@ namespace {
 constexpr int BIS_NS = 16;       // shifts per eigenvalue
 constexpr int BIS_CH = 2048;     // alpha^2 chunk staged in LDS
 
-__global__ void k_alpha2(const double *__restrict__ alpha, int n, double *__restrict__ a2,
-                         double *__restrict__ stats, const double *__restrict__ diag)
+// The kernels below serve one problem (probs null: the problem is `one`,
+// blockIdx.x its block index) or a batch: probs[p] for p = 0..cnt-1, where
+// block g belongs to the problem p with pre[p] <= g < pre[p + 1] (a prefix
+// table of the problems' block counts) as its block g - pre[p].  The same
+// code runs either way, so batched results equal single ones bitwise.
+__device__ __forceinline__ int find_prob(const int *pre, int cnt, int g)
 {
-    // a2[i] = alpha[i]^2 (i < n-1); stats[0] = ||T||_inf, stats[1] = max alpha^2
+    int lo = 0, hi = cnt;   // pre[lo] <= g < pre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// the problem of this block and the block's index within it
+__device__ __forceinline__ skew::TriProb tri_prob(const skew::TriProb &one, const skew::TriProb *probs,
+                                                  const int *pre, int cnt, int &bx)
+{
+    bx = blockIdx.x;
+    if (!probs) return one;
+    const int p = __builtin_amdgcn_readfirstlane(pre ? find_prob(pre, cnt, bx) : bx);
+    if (pre) bx -= pre[p];
+    else bx = 0;
+    return probs[p];
+}
+
+// One block per problem.  With the band given (Q.ab), alpha is first taken
+// from it (alpha_j = -A[j+1, j]; a 1 x 1 problem gets alpha_0 = 0).  Then
+// a2[i] = alpha[i]^2 (i < n-1), stats[0] = ||T||_inf, stats[1] = max alpha^2.
+__global__ void k_alpha2(skew::TriProb one, const skew::TriProb *__restrict__ probs)
+{
     __shared__ double mx[256], mg[256];
+    int bx;
+    const skew::TriProb Q = tri_prob(one, probs, nullptr, 0, bx);
+    const int n = Q.n;
+    double *__restrict__ alpha = Q.alpha;
+    const double *__restrict__ diag = Q.diag;
+    if (Q.ab) {
+        for (int j = threadIdx.x; j < n - 1; j += 256) alpha[j] = -Q.ab[(size_t)j * Q.ldab + 1];
+        if (n == 1 && threadIdx.x == 0) alpha[0] = 0.0;
+        __syncthreads();
+    }
+    double *__restrict__ a2 = Q.a2;
     double lm = 0.0, lg = 0.0;
     for (int i = threadIdx.x; i < n - 1; i += 256) {
         double a = alpha[i];
@@ -61,19 +101,25 @@ __global__ void k_alpha2(const double *__restrict__ alpha, int n, double *__rest
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        stats[0] = mg[0];
-        stats[1] = mx[0];
+        Q.stats[0] = mg[0];
+        Q.stats[1] = mx[0];
     }
 }
 
 // 256 threads = 16 eigenvalues x 16 shifts.  Eigenvalue index first + e.
-__global__ __launch_bounds__(256) void k_bisect(const double *__restrict__ a2, int n, int first, int count,
-                                                const double *__restrict__ stats, int rounds,
-                                                double *__restrict__ w, const double *__restrict__ diag)
+__global__ __launch_bounds__(256) void k_bisect(skew::TriProb one, const skew::TriProb *__restrict__ probs,
+                                                const int *__restrict__ pre, int cnt, int rounds)
 {
     __shared__ double sa[BIS_CH], sd[BIS_CH];
+    int bx;
+    const skew::TriProb Q = tri_prob(one, probs, pre, cnt, bx);
+    const double *__restrict__ a2 = Q.a2;
+    const double *__restrict__ stats = Q.stats;
+    const double *__restrict__ diag = Q.diag;
+    double *__restrict__ w = Q.w;
+    const int n = Q.n, first = Q.first, count = Q.nev;
     const int q = threadIdx.x & (BIS_NS - 1);
-    const int e = blockIdx.x * (256 / BIS_NS) + threadIdx.x / BIS_NS;
+    const int e = bx * (256 / BIS_NS) + threadIdx.x / BIS_NS;
     const bool active = e < count;
     const int idx = first + (active ? e : 0);
     const double g = stats[0];
@@ -163,16 +209,27 @@ __device__ __forceinline__ double hash_uniform(unsigned long long seed, unsigned
 constexpr int IV_CH = 32;
 constexpr unsigned ERR_INVIT = 8u;
 
-__global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, int n, int nev,
-                                              const double *__restrict__ w,
-                                              const double *__restrict__ stats, int iters,
-                                              double *__restrict__ U0, double *__restrict__ U1,
-                                              double *__restrict__ U2, double *__restrict__ Lm,
-                                              unsigned char *__restrict__ Sw, double *__restrict__ Y,
-                                              double *__restrict__ fac, double ctol, unsigned *err,
-                                              const double *__restrict__ shifts, const double *__restrict__ diag)
+__global__ __launch_bounds__(64) void k_invit(skew::TriProb one, const skew::TriProb *__restrict__ probs,
+                                              const int *__restrict__ pre, int cnt)
 {
-    const int k = blockIdx.x * 64 + threadIdx.x;
+    int bx;
+    const skew::TriProb Q = tri_prob(one, probs, pre, cnt, bx);
+    const double *__restrict__ alpha = Q.alpha;
+    const double *__restrict__ w = Q.w;
+    const double *__restrict__ stats = Q.stats;
+    double *__restrict__ U0 = Q.U0;
+    double *__restrict__ U1 = Q.U1;
+    double *__restrict__ U2 = Q.U2;
+    double *__restrict__ Lm = Q.Lm;
+    unsigned char *__restrict__ Sw = Q.Sw;
+    double *__restrict__ Y = Q.Y;
+    double *__restrict__ fac = Q.fac;
+    const double *__restrict__ shifts = Q.shifts;
+    const double *__restrict__ diag = Q.diag;
+    unsigned *err = Q.err;
+    const double ctol = Q.ctol;
+    const int n = Q.n, nev = Q.nev, iters = Q.iters;
+    const int k = bx * 64 + threadIdx.x;
     if (k >= nev) return;
     const size_t st = nev;
     const double g = stats[0];
@@ -320,10 +377,15 @@ __global__ __launch_bounds__(64) void k_invit(const double *__restrict__ alpha, 
 // Odd n, lambda_0 = 0: q_0 = 1, q_{2m+2} = -alpha_{2m} q_{2m} / alpha_{2m+1},
 // odd entries 0; used only when every alpha_{2m+1} != 0 (else the inverse
 // iteration result stays).  Single thread; writes column 0 of Y ([i][k]).
-__global__ void k_nullvec(const double *__restrict__ alpha, int n, int nev, double *__restrict__ Y,
-                          double *__restrict__ fac)
+__global__ void k_nullvec(skew::TriProb one, const skew::TriProb *__restrict__ probs)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int bx;
+    const skew::TriProb P = tri_prob(one, probs, nullptr, 0, bx);
+    const double *__restrict__ alpha = P.alpha;
+    double *__restrict__ Y = P.Y;
+    double *__restrict__ fac = P.fac;
+    const int n = P.n, nev = P.nev;
+    if (threadIdx.x != 0 || bx != 0 || !(n & 1) || P.diag || nev <= 0) return;
     for (int i = 1; i < n - 1; i += 2)
         if (alpha[i] == 0.0) return;
     const size_t st = nev;
@@ -349,11 +411,18 @@ __global__ void k_nullvec(const double *__restrict__ alpha, int n, int nev, doub
 
 // Y ([i][k], n x nev) -> Q (column-major, ldq), row i of column k scaled by
 // fac[k] (even i) or fac[nev + k] (odd i)
-__global__ void k_transpose(const double *__restrict__ Y, int n, int nev, const double *__restrict__ fac,
-                            double *__restrict__ Q, int ldq)
+__global__ void k_transpose(skew::TriProb one, const skew::TriProb *__restrict__ probs, const int *__restrict__ pre,
+                            int cnt)
 {
     __shared__ double tile[32][33];
-    const int k0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+    int bx;
+    const skew::TriProb P = tri_prob(one, probs, pre, cnt, bx);
+    const double *__restrict__ Y = P.Y;
+    const double *__restrict__ fac = P.fac;
+    double *__restrict__ Q = P.Q;
+    const int n = P.n, nev = P.nev, ldq = P.ldq;
+    const int nbx = (nev + 31) / 32;   // blocks: nbx columns of tiles by row tiles
+    const int k0 = (bx % nbx) * 32, i0 = (bx / nbx) * 32;
     const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
     for (int r = ty; r < 32; r += 8) {
         int i = i0 + r, k = k0 + tx;
@@ -445,14 +514,35 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ Gp,
 
 namespace skew {
 
+int tri_bisect_groups(int nev) { return nev > 0 ? (int)cdiv(nev, 256 / BIS_NS) : 0; }
+int tri_invit_groups(int nev) { return nev > 0 ? (int)cdiv(nev, 64) : 0; }
+int tri_transpose_groups(int n, int nev) { return (nev > 0 && n > 0) ? (int)(cdiv(nev, 32) * cdiv(n, 32)) : 0; }
+
+constexpr int BIS_ROUNDS = 14;   // 17^14 > 2^57
+
+static TriProb tri_one(const double *alpha, int n, int nev, const double *w, const double *stats)
+{
+    TriProb t{};
+    t.alpha = const_cast<double *>(alpha);
+    t.n = n;
+    t.first = n / 2;
+    t.nev = nev;
+    t.w = const_cast<double *>(w);
+    t.stats = const_cast<double *>(stats);
+    return t;
+}
+
 void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, double *a2, double *stats,
                             double *w, hipStream_t st, const double *diag)
 {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_alpha2, dim3(1), dim3(256), 0, st, alpha, n, a2, stats, diag);
-    const int rounds = 14;   // 17^14 > 2^57
-    hipLaunchKernelGGL(k_bisect, dim3(cdiv(count, 256 / BIS_NS)), dim3(256), 0, st, (const double *)a2, n, first,
-                       count, (const double *)stats, rounds, w, diag);
+    TriProb t = tri_one(alpha, n, count, w, stats);
+    t.first = first;
+    t.a2 = a2;
+    t.diag = diag;
+    hipLaunchKernelGGL(k_alpha2, dim3(1), dim3(256), 0, st, t, (const TriProb *)nullptr);
+    hipLaunchKernelGGL(k_bisect, dim3(tri_bisect_groups(count)), dim3(256), 0, st, t, (const TriProb *)nullptr,
+                       (const int *)nullptr, 0, BIS_ROUNDS);
 }
 
 void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
@@ -461,11 +551,25 @@ void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w
                             const double *diag)
 {
     if (nev <= 0) return;
-    hipLaunchKernelGGL(k_invit, dim3(cdiv(nev, 64)), dim3(64), 0, st, alpha, n, nev, w, stats, 3, U0, U1, U2,
-                       Lm, Sw, Y, fac, ctol, err, (const double *)nullptr, diag);
-    if ((n & 1) && !diag) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, alpha, n, nev, Y, fac);
-    hipLaunchKernelGGL(k_transpose, dim3(cdiv(nev, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Y, n,
-                       nev, (const double *)fac, Q, ldq);
+    TriProb t = tri_one(alpha, n, nev, w, stats);
+    t.U0 = U0;
+    t.U1 = U1;
+    t.U2 = U2;
+    t.Lm = Lm;
+    t.Sw = Sw;
+    t.Y = Y;
+    t.fac = fac;
+    t.Q = Q;
+    t.ldq = ldq;
+    t.ctol = ctol;
+    t.err = err;
+    t.diag = diag;
+    t.iters = 3;
+    hipLaunchKernelGGL(k_invit, dim3(tri_invit_groups(nev)), dim3(64), 0, st, t, (const TriProb *)nullptr,
+                       (const int *)nullptr, 0);
+    if ((n & 1) && !diag) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, t, (const TriProb *)nullptr);
+    hipLaunchKernelGGL(k_transpose, dim3(tri_transpose_groups(n, nev)), dim3(32, 8), 0, st, t,
+                       (const TriProb *)nullptr, (const int *)nullptr, 0);
 }
 
 // One more inverse-iteration step for the columns Q[:, 0..m) (eigenvalues
@@ -479,10 +583,39 @@ void launch_tridiag_polish(const double *alpha, int n, int m, const double *w, c
     if (m <= 0) return;
     hipLaunchKernelGGL(k_transpose_in, dim3(cdiv(m, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Q, ldq, n,
                        m, Y);
-    hipLaunchKernelGGL(k_invit, dim3(cdiv(m, 64)), dim3(64), 0, st, alpha, n, m, w, stats, 1, U0, U1, U2, Lm, Sw,
-                       Y, fac, 1e300, (unsigned *)nullptr, shifts, diag);
-    hipLaunchKernelGGL(k_transpose, dim3(cdiv(m, 32), cdiv(n, 32)), dim3(32, 8), 0, st, (const double *)Y, n, m,
-                       (const double *)fac, Q, ldq);
+    TriProb t = tri_one(alpha, n, m, w, stats);
+    t.U0 = U0;
+    t.U1 = U1;
+    t.U2 = U2;
+    t.Lm = Lm;
+    t.Sw = Sw;
+    t.Y = Y;
+    t.fac = fac;
+    t.Q = Q;
+    t.ldq = ldq;
+    t.ctol = 1e300;
+    t.err = nullptr;
+    t.shifts = shifts;
+    t.diag = diag;
+    t.iters = 1;
+    hipLaunchKernelGGL(k_invit, dim3(tri_invit_groups(m)), dim3(64), 0, st, t, (const TriProb *)nullptr,
+                       (const int *)nullptr, 0);
+    hipLaunchKernelGGL(k_transpose, dim3(tri_transpose_groups(n, m)), dim3(32, 8), 0, st, t,
+                       (const TriProb *)nullptr, (const int *)nullptr, 0);
+}
+
+void launch_tridiag_batched(const TriProb *probs, const int *pre, int cnt, const int tot[3], hipStream_t st)
+{
+    if (cnt <= 0) return;
+    const TriProb none{};
+    hipLaunchKernelGGL(k_alpha2, dim3(cnt), dim3(256), 0, st, none, probs);
+    if (tot[0] > 0)
+        hipLaunchKernelGGL(k_bisect, dim3(tot[0]), dim3(256), 0, st, none, probs, pre, cnt, BIS_ROUNDS);
+    if (tot[1] > 0)
+        hipLaunchKernelGGL(k_invit, dim3(tot[1]), dim3(64), 0, st, none, probs, pre + (cnt + 1), cnt);
+    hipLaunchKernelGGL(k_nullvec, dim3(cnt), dim3(64), 0, st, none, probs);
+    if (tot[2] > 0)
+        hipLaunchKernelGGL(k_transpose, dim3(tot[2]), dim3(32, 8), 0, st, none, probs, pre + 2 * (cnt + 1), cnt);
 }
 
 void launch_degenerate_check(const double *w, int m, const double *stats, double tol, unsigned *flag,
