@@ -464,13 +464,19 @@ int stage_band(skew_evd_handle h, const Plan &p, const Layout &L, const double *
                 else
                     return skew::launch_gemm_tn_part<T>(X, ldx, X, ldx, b, b, m, Gq, st, cholqr_splits(m));
             };
-            int S = gram(P, n);
-            skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
-            skew::launch_chol_qr(b, 1, cq, qf, st);
+            // few partials are summed by the Cholesky kernel itself, many by
+            // a parallel reduction first (the same order of summation)
+            auto chol = [&](int S, int pass) {
+                if (S <= 16) {
+                    skew::launch_chol_qr(b, pass, cq, qf, st, Gq, S);
+                } else {
+                    skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
+                    skew::launch_chol_qr(b, pass, cq, qf, st);
+                }
+            };
+            chol(gram(P, n), 1);
             skew::launch_gemm_nn<T>(P, n, cq + skew::CQ_R1INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
-            S = gram(Vq, m);
-            skew::launch_gram_reduce(Gq, S, b * b, cq + skew::CQ_G * BB, st);
-            skew::launch_chol_qr(b, 2, cq, qf, st);
+            chol(gram(Vq, m), 2);
             skew::launch_gemm_nn<T>(Vq, m, cq + skew::CQ_R2INV * BB, 1, m, b, b, Vq, m, 1.0, 0, st);
             skew::launch_hh_rebuild<T>(Vq, m, b, P, n, cq, Tf, tauj, qf, st);
             if (m > b)

@@ -446,8 +446,9 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ 
     G[e] = s;
 }
 
-// Cholesky factor R (upper, G = R^T R) and R^{-1} of the Gram matrix in
-// cq[CQ_G].  pass 1: R1, R1^{-1}; flag = 1 when a pivot falls below
+// Cholesky factor R (upper, G = R^T R) and R^{-1} of the Gram matrix: the
+// sum of the np partials Gp (each B x B, summed in order, as
+// k_gram_reduce does), or cq[CQ_G] when Gp is null.  pass 1: R1, R1^{-1}; flag = 1 when a pivot falls below
 // 1e-13 max_i G_ii (condition of the panel beyond what two passes restore).
 // pass 2 (skipped when the flag is set): R2^{-1} and R = R2 R1.  There
 // G2 = I + E; when max |E_ij| <= 1e-8 the factor is taken to first order,
@@ -455,7 +456,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ 
 // upper(E), whose neglected terms are O(|E|^2) <= 1e-16; otherwise R2 is
 // factored, and flag = 1 when a pivot leaves (0.5, 2).
 __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__restrict__ cq,
-                                                 unsigned *__restrict__ flag)
+                                                 unsigned *__restrict__ flag, const double *__restrict__ Gp,
+                                                 int np)
 {
     __shared__ double M[64 * 65], X[64 * 65], R1s[64 * 65], part[4];
     __shared__ __attribute__((aligned(16))) double buf[320];
@@ -469,7 +471,14 @@ __global__ __launch_bounds__(256) void k_chol_qr(int B, int pass, double *__rest
     for (int q = 0; q < 16; ++q) {
         const int j = ty + 4 * q;
         const bool in = tx < B && j < B;
-        const double gv = in ? G[(size_t)j * B + tx] : 0.0;
+        double gv = 0.0;
+        if (in) {
+            if (Gp) {
+                for (int p = 0; p < np; ++p) gv += Gp[(size_t)p * B * B + (size_t)j * B + tx];
+            } else {
+                gv = G[(size_t)j * B + tx];
+            }
+        }
         M[tx * 65 + j] = gv;
         if (pass == 2) {
             R1s[tx * 65 + j] = in ? R1[(size_t)j * B + tx] : 0.0;
@@ -729,9 +738,9 @@ void launch_gram_reduce(const double *Gp, int np, int BB, double *G, hipStream_t
 {
     hipLaunchKernelGGL(k_gram_reduce, dim3(cdiv(BB, 256)), dim3(256), 0, st, Gp, np, BB, G);
 }
-void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st)
+void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st, const double *Gp, int np)
 {
-    hipLaunchKernelGGL(k_chol_qr, dim3(1), dim3(256), 0, st, B, pass, cq, flag);
+    hipLaunchKernelGGL(k_chol_qr, dim3(1), dim3(256), 0, st, B, pass, cq, flag, Gp, np);
 }
 template <typename T>
 void launch_hh_rebuild(T *Vd, int m, int B, T *Wp, int ldw, double *cq, double *Tf, double *tau,

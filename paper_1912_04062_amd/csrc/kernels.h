@@ -22,7 +22,9 @@ hipError_t launch_panel_qr(T *W, int ldw, int c0, int r0, int m, int B, T *Vd, d
 constexpr int CQ_G = 0, CQ_R1 = 1, CQ_R1INV = 2, CQ_R2INV = 3, CQ_R = 4, CQ_UINV = 5;
 size_t cholqr_scratch_doubles();
 void launch_gram_reduce(const double *Gp, int np, int BB, double *G, hipStream_t st);
-void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st);
+// Gp non-null: the Gram matrix is the sum of its np partials (summed here)
+void launch_chol_qr(int B, int pass, double *cq, unsigned *flag, hipStream_t st, const double *Gp = nullptr,
+                    int np = 0);
 template <typename T>
 void launch_hh_rebuild(T *Vd, int m, int B, T *Wp, int ldw, double *cq, double *Tf, double *tau,
                        const unsigned *flag, hipStream_t st);

@@ -228,6 +228,29 @@ def test_batched_mixed_problems(h):
             assert c["colres"] <= 1e-12 and c["orth_max"] <= 1e-12, (k, c)
 
 
+def test_batched_empty_spectra(h):
+    """Problems asking for no eigenpairs beside ones that do: the batched
+    tridiagonal launches map workgroups to problems through prefix tables of
+    their block counts, in which a problem without eigenpairs has none.  The
+    others are bitwise equal to their single solves."""
+    import torch
+    print("batched empty spectra", flush=True)
+    sizes = [64, 65, 300, 2, 257, 130]
+    nevs = [0, 33, 0, 1, 0, 40]
+    mats = [wl.random_skew(n, 640 + k) for k, n in enumerate(sizes)]
+    dev = [to_dev(A) for A in mats]
+    res, status, st = h.solve_batched(dev, nevs=nevs)
+    torch.cuda.synchronize()
+    assert st == 0 and all(s == 0 for s in status), status
+    for k, (Ad, nv, (lam, zr, zi)) in enumerate(zip(dev, nevs, res)):
+        assert lam.numel() == nv and zr.shape[1] == nv, k
+        if nv == 0:
+            continue
+        l1, r1, i1 = h.solve(Ad, nev=nv)
+        torch.cuda.synchronize()
+        assert torch.equal(lam, l1) and torch.equal(zr, r1) and torch.equal(zi, i1), k
+
+
 @pytest.mark.parametrize("n,precision", [(300, "fp64"), (301, "fp64"), (257, "fp32")])
 def test_all_pairs(h, n, precision):
     """opts.all_pairs: every eigenpair of both signs, ascending, the exact zero
