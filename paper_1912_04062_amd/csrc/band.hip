@@ -699,7 +699,16 @@ void launch_stage1_w(T *W, int ldw, int r0, int m, int B, const T *Vd, const dou
     else
         hipLaunchKernelGGL((k_gram<T, 32>), dim3(nch), dim3(256), (gemm::smem_bytes<T, 32, 32>()), st,
                            (const T *)Vd, (const T *)Y0, m, B, rc, Gp);
-    hipLaunchKernelGGL(k_small<T>, dim3(1), dim3(256), 0, st, (const double *)Gp, nch, B, Tf, Tx);
+    if (nch > 16) {
+        // many partials: a parallel reduction first, into the spare block
+        // after them (the buffer holds m / rc + 2 blocks)
+        double *G1 = Gp + (size_t)nch * B * B;
+        hipLaunchKernelGGL(k_gram_reduce, dim3(cdiv(B * B, 256)), dim3(256), 0, st, (const double *)Gp, nch, B * B,
+                           G1);
+        hipLaunchKernelGGL(k_small<T>, dim3(1), dim3(256), 0, st, (const double *)G1, 1, B, Tf, Tx);
+    } else {
+        hipLaunchKernelGGL(k_small<T>, dim3(1), dim3(256), 0, st, (const double *)Gp, nch, B, Tf, Tx);
+    }
     if (B > 32)
         hipLaunchKernelGGL((k_wform<T, 64>), dim3(cdiv(m, 64)), dim3(256), (gemm::smem_bytes<T, 64, 64>()), st,
                            (const T *)Y0, Vd, (const T *)Tx, m, B, Wd);
