@@ -1606,7 +1606,7 @@ skew::TriProb tri_prob(char *w, const BatchItem &it)
     t.first = p.n / 2;
     t.nev = p.nev;
     t.ldq = p.n;
-    t.iters = 3;
+    t.iters = 2;
     return t;
 }
 

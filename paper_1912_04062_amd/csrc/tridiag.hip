@@ -47,16 +47,68 @@ __device__ __forceinline__ int find_prob(const int *pre, int cnt, int g)
     return lo;
 }
 
+// A descriptor's pointers as global-address-space pointers (pointers read
+// from memory would otherwise compile to flat accesses, which also wait on
+// the LDS counter).
+template <typename T> using gp = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gp<T> gptr(T *p) { return (gp<T>)p; }
+template <typename T> __device__ __forceinline__ gp<const T> gptr(const T *p) { return (gp<const T>)p; }
+
+// Every field of a descriptor is the same in all lanes of a block: stated to
+// the compiler, so that sizes and pointers live in scalar registers (loop
+// bounds stay scalar, loads take a scalar base).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T> __device__ __forceinline__ T *uni(T *p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (T *)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double uni(double d)
+{
+    const unsigned long long v = __double_as_longlong(d);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // the problem of this block and the block's index within it
 __device__ __forceinline__ skew::TriProb tri_prob(const skew::TriProb &one, const skew::TriProb *probs,
                                                   const int *pre, int cnt, int &bx)
 {
     bx = blockIdx.x;
-    if (!probs) return one;
-    const int p = __builtin_amdgcn_readfirstlane(pre ? find_prob(pre, cnt, bx) : bx);
-    if (pre) bx -= pre[p];
-    else bx = 0;
-    return probs[p];
+    skew::TriProb t = one;
+    if (probs) {
+        const int p = uni(pre ? find_prob(pre, cnt, bx) : bx);
+        bx = pre ? bx - uni(pre[p]) : 0;
+        t = probs[p];
+    }
+    skew::TriProb u;
+    u.ab = uni(t.ab);
+    u.alpha = uni(t.alpha);
+    u.a2 = uni(t.a2);
+    u.stats = uni(t.stats);
+    u.w = uni(t.w);
+    u.U0 = uni(t.U0);
+    u.U1 = uni(t.U1);
+    u.U2 = uni(t.U2);
+    u.Lm = uni(t.Lm);
+    u.Y = uni(t.Y);
+    u.fac = uni(t.fac);
+    u.Q = uni(t.Q);
+    u.Sw = uni(t.Sw);
+    u.err = uni(t.err);
+    u.diag = uni(t.diag);
+    u.shifts = uni(t.shifts);
+    u.ctol = uni(t.ctol);
+    u.ldab = uni(t.ldab);
+    u.n = uni(t.n);
+    u.first = uni(t.first);
+    u.nev = uni(t.nev);
+    u.ldq = uni(t.ldq);
+    u.iters = uni(t.iters);
+    return u;
 }
 
 // One block per problem.  With the band given (Q.ab), alpha is first taken
@@ -68,14 +120,15 @@ __global__ void k_alpha2(skew::TriProb one, const skew::TriProb *__restrict__ pr
     int bx;
     const skew::TriProb Q = tri_prob(one, probs, nullptr, 0, bx);
     const int n = Q.n;
-    double *__restrict__ alpha = Q.alpha;
-    const double *__restrict__ diag = Q.diag;
+    const gp<double> __restrict__ alpha = gptr(Q.alpha);
+    const gp<const double> __restrict__ diag = gptr(Q.diag);
     if (Q.ab) {
-        for (int j = threadIdx.x; j < n - 1; j += 256) alpha[j] = -Q.ab[(size_t)j * Q.ldab + 1];
+        const gp<const double> ab = gptr(Q.ab);
+        for (int j = threadIdx.x; j < n - 1; j += 256) alpha[j] = -ab[(size_t)j * Q.ldab + 1];
         if (n == 1 && threadIdx.x == 0) alpha[0] = 0.0;
         __syncthreads();
     }
-    double *__restrict__ a2 = Q.a2;
+    const gp<double> __restrict__ a2 = gptr(Q.a2);
     double lm = 0.0, lg = 0.0;
     for (int i = threadIdx.x; i < n - 1; i += 256) {
         double a = alpha[i];
@@ -101,8 +154,9 @@ __global__ void k_alpha2(skew::TriProb one, const skew::TriProb *__restrict__ pr
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        Q.stats[0] = mg[0];
-        Q.stats[1] = mx[0];
+        const gp<double> stats = gptr(Q.stats);
+        stats[0] = mg[0];
+        stats[1] = mx[0];
     }
 }
 
@@ -113,10 +167,12 @@ __global__ __launch_bounds__(256) void k_bisect(skew::TriProb one, const skew::T
     __shared__ double sa[BIS_CH], sd[BIS_CH];
     int bx;
     const skew::TriProb Q = tri_prob(one, probs, pre, cnt, bx);
-    const double *__restrict__ a2 = Q.a2;
-    const double *__restrict__ stats = Q.stats;
-    const double *__restrict__ diag = Q.diag;
-    double *__restrict__ w = Q.w;
+    const gp<const double> __restrict__ a2 = gptr(Q.a2);
+    const gp<const double> __restrict__ stats = gptr(Q.stats);
+    // the diagonal's presence is uniform: a scalar branch
+    const gp<const double> __restrict__ diag =
+        __builtin_amdgcn_readfirstlane((int)(Q.diag != nullptr)) ? gptr(Q.diag) : nullptr;
+    const gp<double> __restrict__ w = gptr(Q.w);
     const int n = Q.n, first = Q.first, count = Q.nev;
     const int q = threadIdx.x & (BIS_NS - 1);
     const int e = bx * (256 / BIS_NS) + threadIdx.x / BIS_NS;
@@ -214,18 +270,21 @@ __global__ __launch_bounds__(64) void k_invit(skew::TriProb one, const skew::Tri
 {
     int bx;
     const skew::TriProb Q = tri_prob(one, probs, pre, cnt, bx);
-    const double *__restrict__ alpha = Q.alpha;
-    const double *__restrict__ w = Q.w;
-    const double *__restrict__ stats = Q.stats;
-    double *__restrict__ U0 = Q.U0;
-    double *__restrict__ U1 = Q.U1;
-    double *__restrict__ U2 = Q.U2;
-    double *__restrict__ Lm = Q.Lm;
-    unsigned char *__restrict__ Sw = Q.Sw;
-    double *__restrict__ Y = Q.Y;
-    double *__restrict__ fac = Q.fac;
-    const double *__restrict__ shifts = Q.shifts;
-    const double *__restrict__ diag = Q.diag;
+    const gp<const double> __restrict__ alpha = gptr(Q.alpha);
+    const gp<const double> __restrict__ w = gptr(Q.w);
+    const gp<const double> __restrict__ stats = gptr(Q.stats);
+    const gp<double> __restrict__ U0 = gptr(Q.U0);
+    const gp<double> __restrict__ U1 = gptr(Q.U1);
+    const gp<double> __restrict__ U2 = gptr(Q.U2);
+    const gp<double> __restrict__ Lm = gptr(Q.Lm);
+    const gp<unsigned char> __restrict__ Sw = gptr(Q.Sw);
+    const gp<double> __restrict__ Y = gptr(Q.Y);
+    const gp<double> __restrict__ fac = gptr(Q.fac);
+    // presence of shifts and diagonal is uniform: scalar branches
+    const gp<const double> __restrict__ shifts =
+        __builtin_amdgcn_readfirstlane((int)(Q.shifts != nullptr)) ? gptr(Q.shifts) : nullptr;
+    const gp<const double> __restrict__ diag =
+        __builtin_amdgcn_readfirstlane((int)(Q.diag != nullptr)) ? gptr(Q.diag) : nullptr;
     unsigned *err = Q.err;
     const double ctol = Q.ctol;
     const int n = Q.n, nev = Q.nev, iters = Q.iters;
@@ -381,9 +440,9 @@ __global__ void k_nullvec(skew::TriProb one, const skew::TriProb *__restrict__ p
 {
     int bx;
     const skew::TriProb P = tri_prob(one, probs, nullptr, 0, bx);
-    const double *__restrict__ alpha = P.alpha;
-    double *__restrict__ Y = P.Y;
-    double *__restrict__ fac = P.fac;
+    const gp<const double> __restrict__ alpha = gptr(P.alpha);
+    const gp<double> __restrict__ Y = gptr(P.Y);
+    const gp<double> __restrict__ fac = gptr(P.fac);
     const int n = P.n, nev = P.nev;
     if (threadIdx.x != 0 || bx != 0 || !(n & 1) || P.diag || nev <= 0) return;
     for (int i = 1; i < n - 1; i += 2)
@@ -417,9 +476,9 @@ __global__ void k_transpose(skew::TriProb one, const skew::TriProb *__restrict__
     __shared__ double tile[32][33];
     int bx;
     const skew::TriProb P = tri_prob(one, probs, pre, cnt, bx);
-    const double *__restrict__ Y = P.Y;
-    const double *__restrict__ fac = P.fac;
-    double *__restrict__ Q = P.Q;
+    const gp<const double> __restrict__ Y = gptr(P.Y);
+    const gp<const double> __restrict__ fac = gptr(P.fac);
+    const gp<double> __restrict__ Q = gptr(P.Q);
     const int n = P.n, nev = P.nev, ldq = P.ldq;
     const int nbx = (nev + 31) / 32;   // blocks: nbx columns of tiles by row tiles
     const int k0 = (bx % nbx) * 32, i0 = (bx / nbx) * 32;
@@ -564,7 +623,7 @@ void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w
     t.ctol = ctol;
     t.err = err;
     t.diag = diag;
-    t.iters = 3;
+    t.iters = 2;
     hipLaunchKernelGGL(k_invit, dim3(tri_invit_groups(nev)), dim3(64), 0, st, t, (const TriProb *)nullptr,
                        (const int *)nullptr, 0);
     if ((n & 1) && !diag) hipLaunchKernelGGL(k_nullvec, dim3(1), dim3(64), 0, st, t, (const TriProb *)nullptr);
