@@ -107,7 +107,7 @@ namespace {
 // Workspace layout.  Offsets are 256-byte aligned.
 struct Layout {
     size_t W, Vall, Tall, tauall, Ypart, Y0, Wd, Gp, Tx, part, ab, goff, V2, tau2, T2, V2t, alpha, a2, stats,
-        lam, U0, U1, U2, Lm, Sw, Yiv, ivfac, pshift, Qd, Z, Wos, oss, Wim, Vim, Tim, tauc, Wosi, dgl, Wp2, cq, cqGp, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
+        lam, gcnt, U0, U1, U2, Lm, Sw, Yiv, ivfac, pshift, Qd, Z, Wos, oss, Wim, Vim, Tim, tauc, Wosi, dgl, Wp2, cq, cqGp, Wp, Wt2, Pp, P, Gp2, Rinv, Tmp, ctl, rX, rXn, rP, rS, rG, rE, rlam,
         rstat, Tm, total;
 };
 
@@ -169,6 +169,7 @@ Layout plan_layout(const Plan &p)
     L.a2 = take(sizeof(double) * n);
     L.stats = take(sizeof(double) * 4);
     L.lam = take(sizeof(double) * nev);
+    L.gcnt = take(sizeof(int) * (size_t)skew::tri_grid_points((int)nev));
     L.U0 = take(sizeof(double) * n * nev);
     L.U1 = take(sizeof(double) * n * nev);
     L.U2 = take(sizeof(double) * n * nev);
@@ -798,7 +799,7 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
     const int n = p.n;
     HCHK(kt_begin(h, SKEW_EVD_K_TRIDIAG));
     skew::launch_tridiag_eigvals(alpha, n, n / 2, nev, ptr<double>(h, L.a2), ptr<double>(h, L.stats), lam, st,
-                                 diag);
+                                 diag, ptr<int>(h, L.gcnt));
     int rc = fetch_windows(h, p, L, lam, nev);
     if (rc) return rc;
     if (early_t) {
@@ -1598,6 +1599,7 @@ skew::TriProb tri_prob(char *w, const BatchItem &it)
     t.Q = (double *)(w + L.Qd);
     t.Sw = (unsigned char *)(w + L.Sw);
     t.err = (unsigned *)(w + L.ctl) + CTL_ERR;
+    t.gcnt = (int *)(w + L.gcnt);
     t.diag = nullptr;
     t.shifts = nullptr;
     t.ctol = INVIT_CTOL;

@@ -65,8 +65,10 @@ void launch_goff(int n, int b, int nb2, int *goff, hipStream_t st);
 // tridiag.hip
 // diag: the diagonal of a general symmetric tridiagonal matrix (n entries),
 // or null for the zero diagonal of Lemma 1
+// gcnt: tri_grid_points(count) ints for the grid pre-pass (null: none)
 void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, double *a2, double *stats,
-                            double *w, hipStream_t st, const double *diag = nullptr);
+                            double *w, hipStream_t st, const double *diag = nullptr, int *gcnt = nullptr);
+int tri_grid_points(int nev);
 void launch_tridiag_eigvecs(const double *alpha, int n, int nev, const double *w, const double *stats,
                             double *U0, double *U1, double *U2, double *Lm, unsigned char *Sw, double *Y,
                             double *fac, double *Q, int ldq, double ctol, unsigned *err, hipStream_t st,
@@ -84,6 +86,7 @@ struct TriProb {
     double *U0, *U1, *U2, *Lm, *Y, *fac, *Q;
     unsigned char *Sw;
     unsigned *err;
+    int *gcnt;                  // counts of the bisection's grid pre-pass (null: none)
     const double *diag, *shifts;
     double ctol;
     int ldab, n, first, nev, ldq, iters;

@@ -99,6 +99,7 @@ __device__ __forceinline__ skew::TriProb tri_prob(const skew::TriProb &one, cons
     u.Q = uni(t.Q);
     u.Sw = uni(t.Sw);
     u.err = uni(t.err);
+    u.gcnt = uni(t.gcnt);
     u.diag = uni(t.diag);
     u.shifts = uni(t.shifts);
     u.ctol = uni(t.ctol);
@@ -160,7 +161,81 @@ __global__ void k_alpha2(skew::TriProb one, const skew::TriProb *__restrict__ pr
     }
 }
 
+// Inertia count of T - x I (the eigenvalues below x), by all threads of the
+// block together: alpha^2 (and the diagonal) staged through LDS in chunks.
+__device__ __forceinline__ int sturm_count(double xq, gp<const double> a2, gp<const double> diag, int n,
+                                           double pivmin, double *sa, double *sd)
+{
+    double d = diag ? diag[0] - xq : -xq;
+    if (fabs(d) < pivmin) d = -pivmin;
+    int cnt = (d < 0.0) ? 1 : 0;
+    for (int c0 = 0; c0 < n - 1; c0 += BIS_CH) {
+        const int len = min(BIS_CH, n - 1 - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < len; i += 256) {
+            sa[i] = a2[c0 + i];
+            if (diag) sd[i] = diag[c0 + i + 1];
+        }
+        __syncthreads();
+        if (diag) {
+            for (int i = 0; i < len; ++i) {
+                d = (sd[i] - xq) - sa[i] * recip(d);
+                if (fabs(d) < pivmin) d = -pivmin;
+                cnt += (d < 0.0) ? 1 : 0;
+            }
+        } else {
+            for (int i = 0; i < len; ++i) {
+                d = -xq - sa[i] * recip(d);
+                if (fabs(d) < pivmin) d = -pivmin;
+                cnt += (d < 0.0) ? 1 : 0;
+            }
+        }
+    }
+    return cnt;
+}
+
+// The Gershgorin interval that starts the bisection, and pivmin.
+__device__ __forceinline__ void bis_bounds(gp<const double> stats, double &lo, double &hi, double &pivmin)
+{
+    const double g = stats[0];
+    pivmin = 2.2250738585072014e-308 * fmax(1.0, stats[1]);
+    const double eps = 2.220446049250313e-16;
+    lo = -g * (1.0 + 2.0 * eps) - 2.0 * pivmin;
+    hi = g * (1.0 + 2.0 * eps) + 2.0 * pivmin;
+}
+
+// Points of the grid pre-pass: one per thread of the bisection launch.
+__device__ __forceinline__ int grid_points(int nev) { return 256 * ((nev + (256 / BIS_NS) - 1) / (256 / BIS_NS)); }
+
+// Grid pre-pass of the bisection: the inertia counts at the NP points
+// x_t = lo + (t + 1) h, h = (hi - lo) / (NP + 1), of the Gershgorin
+// interval, one per thread (the bisection's grid).  Each eigenvalue's
+// starting bracket is then the grid interval that holds it, which saves
+// the rounds that would narrow the whole interval down to one grid step.
+__global__ __launch_bounds__(256) void k_gridcount(skew::TriProb one, const skew::TriProb *__restrict__ probs,
+                                                   const int *__restrict__ pre, int cnt)
+{
+    __shared__ double sa[BIS_CH], sd[BIS_CH];
+    int bx;
+    const skew::TriProb Q = tri_prob(one, probs, pre, cnt, bx);
+    if (!Q.gcnt) return;
+    const gp<const double> __restrict__ a2 = gptr(Q.a2);
+    const gp<const double> __restrict__ stats = gptr(Q.stats);
+    const gp<const double> __restrict__ diag =
+        __builtin_amdgcn_readfirstlane((int)(Q.diag != nullptr)) ? gptr(Q.diag) : nullptr;
+    const int NP = grid_points(Q.nev);
+    double lo, hi, pivmin;
+    bis_bounds(stats, lo, hi, pivmin);
+    const double h = (hi - lo) / (NP + 1);
+    const int t = bx * 256 + threadIdx.x;
+    const int c = sturm_count(lo + (t + 1) * h, a2, diag, Q.n, pivmin, sa, sd);
+    gptr(Q.gcnt)[t] = c;
+}
+
 // 256 threads = 16 eigenvalues x 16 shifts.  Eigenvalue index first + e.
+// rounds: for the whole Gershgorin interval; after the grid pre-pass the
+// bracket starts (NP + 1) times narrower and takes only the rounds that
+// bring it below the same width.
 __global__ __launch_bounds__(256) void k_bisect(skew::TriProb one, const skew::TriProb *__restrict__ probs,
                                                 const int *__restrict__ pre, int cnt, int rounds)
 {
@@ -178,39 +253,38 @@ __global__ __launch_bounds__(256) void k_bisect(skew::TriProb one, const skew::T
     const int e = bx * (256 / BIS_NS) + threadIdx.x / BIS_NS;
     const bool active = e < count;
     const int idx = first + (active ? e : 0);
-    const double g = stats[0];
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, stats[1]);
-    const double eps = 2.220446049250313e-16;
-    double lo = -g * (1.0 + 2.0 * eps) - 2.0 * pivmin;
-    double hi = g * (1.0 + 2.0 * eps) + 2.0 * pivmin;
-    for (int r = 0; r < rounds; ++r) {
+    double lo, hi, pivmin;
+    bis_bounds(stats, lo, hi, pivmin);
+    int nr = rounds;
+    if (Q.gcnt) {
+        // the grid interval that holds lambda_idx: the first point whose
+        // count exceeds idx (the counts grow with x)
+        const gp<const int> gc = gptr(Q.gcnt);
+        const int NP = grid_points(count);
+        int a = 0, b = NP;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (gc[mid] > idx) b = mid;
+            else a = mid + 1;
+        }
+        const double h = (hi - lo) / (NP + 1);
+        const double nlo = (a > 0) ? lo + a * h : lo;          // x_{a-1}
+        const double nhi = (a < NP) ? lo + (a + 1) * h : hi;   // x_a
+        lo = nlo;
+        hi = nhi;
+        // rounds until (NP + 1) 17^r reaches 17^rounds
+        double f = NP + 1.0, full = 1.0;
+        for (int r = 0; r < rounds; ++r) full *= (BIS_NS + 1);
+        nr = 0;
+        while (nr < rounds && f < full) {
+            f *= (BIS_NS + 1);
+            ++nr;
+        }
+    }
+    for (int r = 0; r < nr; ++r) {
         const double h = (hi - lo) / (BIS_NS + 1);
         const double xq = lo + (q + 1) * h;
-        double d = diag ? diag[0] - xq : -xq;
-        if (fabs(d) < pivmin) d = -pivmin;
-        int cnt = (d < 0.0) ? 1 : 0;
-        for (int c0 = 0; c0 < n - 1; c0 += BIS_CH) {
-            const int len = min(BIS_CH, n - 1 - c0);
-            __syncthreads();
-            for (int i = threadIdx.x; i < len; i += 256) {
-                sa[i] = a2[c0 + i];
-                if (diag) sd[i] = diag[c0 + i + 1];
-            }
-            __syncthreads();
-            if (diag) {
-                for (int i = 0; i < len; ++i) {
-                    d = (sd[i] - xq) - sa[i] * recip(d);
-                    if (fabs(d) < pivmin) d = -pivmin;
-                    cnt += (d < 0.0) ? 1 : 0;
-                }
-            } else {
-                for (int i = 0; i < len; ++i) {
-                    d = -xq - sa[i] * recip(d);
-                    if (fabs(d) < pivmin) d = -pivmin;
-                    cnt += (d < 0.0) ? 1 : 0;
-                }
-            }
-        }
+        const int cnt = sturm_count(xq, a2, diag, n, pivmin, sa, sd);
         // lanes with count <= idx have lambda_idx >= x_q
         unsigned long long m = __ballot(cnt <= idx);
         const int sh = (threadIdx.x & 63) & ~(BIS_NS - 1);
@@ -591,15 +665,21 @@ static TriProb tri_one(const double *alpha, int n, int nev, const double *w, con
     return t;
 }
 
+int tri_grid_points(int nev) { return 256 * tri_bisect_groups(nev); }
+
 void launch_tridiag_eigvals(const double *alpha, int n, int first, int count, double *a2, double *stats,
-                            double *w, hipStream_t st, const double *diag)
+                            double *w, hipStream_t st, const double *diag, int *gcnt)
 {
     if (count <= 0) return;
     TriProb t = tri_one(alpha, n, count, w, stats);
     t.first = first;
     t.a2 = a2;
     t.diag = diag;
+    t.gcnt = gcnt;
     hipLaunchKernelGGL(k_alpha2, dim3(1), dim3(256), 0, st, t, (const TriProb *)nullptr);
+    if (gcnt)
+        hipLaunchKernelGGL(k_gridcount, dim3(tri_bisect_groups(count)), dim3(256), 0, st, t,
+                           (const TriProb *)nullptr, (const int *)nullptr, 0);
     hipLaunchKernelGGL(k_bisect, dim3(tri_bisect_groups(count)), dim3(256), 0, st, t, (const TriProb *)nullptr,
                        (const int *)nullptr, 0, BIS_ROUNDS);
 }
@@ -668,8 +748,10 @@ void launch_tridiag_batched(const TriProb *probs, const int *pre, int cnt, const
     if (cnt <= 0) return;
     const TriProb none{};
     hipLaunchKernelGGL(k_alpha2, dim3(cnt), dim3(256), 0, st, none, probs);
-    if (tot[0] > 0)
+    if (tot[0] > 0) {
+        hipLaunchKernelGGL(k_gridcount, dim3(tot[0]), dim3(256), 0, st, none, probs, pre, cnt);
         hipLaunchKernelGGL(k_bisect, dim3(tot[0]), dim3(256), 0, st, none, probs, pre, cnt, BIS_ROUNDS);
+    }
     if (tot[1] > 0)
         hipLaunchKernelGGL(k_invit, dim3(tot[1]), dim3(64), 0, st, none, probs, pre + (cnt + 1), cnt);
     hipLaunchKernelGGL(k_nullvec, dim3(cnt), dim3(64), 0, st, none, probs);
