@@ -76,7 +76,8 @@ struct skew_evd_handle_s {
     // second stream: the T factors of the stage-2 groups run on it beside
     // the tridiagonal solve
     hipStream_t aux = nullptr;
-    hipEvent_t aux_ev[3] = {};
+    hipEvent_t aux_ev[4] = {};
+    bool merges_started = false;   // this solve queued the stage-1 merges before the chase
     // batched form: sub-streams with an event each, a fork event, and pinned
     // host images of the batched chase's descriptors and the status words
     std::vector<hipStream_t> sub_streams;
@@ -642,7 +643,12 @@ int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, 
         double *Qb = Q + (size_t)b0 * ldq;
         for (int pass = 0; wl > 0 && pass < passes; ++pass) {
             const double *Qw = Q + (size_t)w0 * ldq;
-            int S = skew::launch_gemm_tn_part<double>(Qw, ldq, Qb, ldq, wl, nb, n, ptr<double>(h, L.Pp), st);
+            // short windows: 128-row chunks (a short chain of K-chunks per
+            // workgroup) as far as the partials' buffer holds them
+            const size_t wmax = std::max((size_t)p.nev, (size_t)ORTH_NB);
+            const int S_req = std::min({128, (int)((size_t)tn_parts_max() * wmax / (size_t)wl), (n + 127) / 128});
+            int S = skew::launch_gemm_tn_part<double>(Qw, ldq, Qb, ldq, wl, nb, n, ptr<double>(h, L.Pp), st,
+                                                      S_req > tn_parts_max() ? S_req : 0);
             skew::launch_gram_reduce(ptr<double>(h, L.Pp), S, wl * nb, ptr<double>(h, L.P), st);
             skew::launch_gemm_nn<double>(Qw, ldq, ptr<double>(h, L.P), 1, n, nb, wl, Qb, ldq, -1.0, 1, st);
         }
@@ -660,7 +666,7 @@ int orthogonalize(skew_evd_handle h, const Plan &p, const Layout &L, double *Q, 
     return SKEW_EVD_OK;
 }
 
-int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L);
+int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L, bool merges_started);
 
 // One-stage reduction (Section 2.3.1): the strict lower triangle into W, then
 // the panels of 64 columns; alpha, the panels' V and T (kept for the
@@ -803,7 +809,7 @@ int stage_tridiag(skew_evd_handle h, const Plan &p, const Layout &L, const doubl
     int rc = fetch_windows(h, p, L, lam, nev);
     if (rc) return rc;
     if (early_t) {
-        rc = start_bt2_factors(h, p, L);
+        rc = start_bt2_factors(h, p, L, h->merges_started);
         if (rc) return rc;
     }
     const double ctol = (h->debug & SKEW_EVD_DEBUG_INVIT_NOCONV) ? 0.0 : INVIT_CTOL;
@@ -894,26 +900,53 @@ void launch_bt1_merges(skew_evd_handle h, const Plan &p, const Layout &L, double
 // inverse iteration of the tridiagonal solve (which occupies few CUs).
 constexpr int EARLY_TFAC_MIN_N = 4096;
 
-int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L)
+int ensure_aux(skew_evd_handle h)
 {
     if (!h->aux) {
         HCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-        for (int i = 0; i < 3; ++i) HCHK(hipEventCreateWithFlags(&h->aux_ev[i], hipEventDisableTiming));
+        for (auto &e : h->aux_ev) HCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
+    return SKEW_EVD_OK;
+}
+
+// The merged T of the stage-1 panel pairs on the second stream, once stage 1
+// is queued: they depend on stage 1 only and run beside the bulge chase
+// (whose workgroups leave CUs free), with their Gram partials in the panel
+// path's buffer (free after stage 1).  aux_ev[2] marks them done.
+// The caller records aux_ev[3] on the main stream once stage 1 is queued and
+// calls this after queueing the chase, so that no work of the main stream is
+// submitted behind the merges.
+int start_bt1_merges(skew_evd_handle h, const Plan &p, const Layout &L)
+{
+    HCHK(hipStreamWaitEvent(h->aux, h->aux_ev[3], 0));
+    if (p.prec) launch_bt1_merges<float>(h, p, L, ptr<double>(h, L.cqGp), h->aux);
+    else launch_bt1_merges<double>(h, p, L, ptr<double>(h, L.cqGp), h->aux);
+    HCHK(hipGetLastError());
+    HCHK(hipEventRecord(h->aux_ev[2], h->aux));
+    return SKEW_EVD_OK;
+}
+
+// The T factors of the stage-2 groups on the second stream, once the
+// bisection is queued (aux_ev[1] marks them done); merges_started: the
+// stage-1 merges were queued there already, else they follow the factors.
+int start_bt2_factors(skew_evd_handle h, const Plan &p, const Layout &L, bool merges_started)
+{
+    int rc = ensure_aux(h);
+    if (rc) return rc;
     HCHK(hipEventRecord(h->aux_ev[0], h->stream));
     HCHK(hipStreamWaitEvent(h->aux, h->aux_ev[0], 0));
     if (p.prec) launch_bt2_factors<float>(h, p, L, h->aux);
     else launch_bt2_factors<double>(h, p, L, h->aux);
     HCHK(hipGetLastError());
     HCHK(hipEventRecord(h->aux_ev[1], h->aux));
-    // then the merged T of the stage-1 panel pairs (stage 1 only), with their
-    // Gram partials in the panel path's buffer (free after stage 1)
-    if (merged_bt1(p)) {
-        if (p.prec) launch_bt1_merges<float>(h, p, L, ptr<double>(h, L.cqGp), h->aux);
-        else launch_bt1_merges<double>(h, p, L, ptr<double>(h, L.cqGp), h->aux);
-        HCHK(hipGetLastError());
+    if (!merges_started) {
+        if (merged_bt1(p)) {
+            if (p.prec) launch_bt1_merges<float>(h, p, L, ptr<double>(h, L.cqGp), h->aux);
+            else launch_bt1_merges<double>(h, p, L, ptr<double>(h, L.cqGp), h->aux);
+            HCHK(hipGetLastError());
+        }
+        HCHK(hipEventRecord(h->aux_ev[2], h->aux));
     }
-    HCHK(hipEventRecord(h->aux_ev[2], h->aux));
     return SKEW_EVD_OK;
 }
 
@@ -1146,7 +1179,11 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     kt_reset(h, o.profile != 0, o.profile == 2 ? SKEW_EVD_K_BT2 : -1);
     bool rec[NSTAGE_EV] = {};
     // work left on the second stream by an earlier call that returned early
-    if (h->aux) HCHK(hipStreamWaitEvent(st, h->aux_ev[2], 0));
+    if (h->aux) {
+        HCHK(hipStreamWaitEvent(st, h->aux_ev[1], 0));
+        HCHK(hipStreamWaitEvent(st, h->aux_ev[2], 0));
+    }
+    h->merges_started = false;
     // test hooks: every workspace byte NaN (0xff) or zero before the solve
     if (o.debug & SKEW_EVD_DEBUG_NAN_WS) skew::launch_fill32(h->ws, 0xffffffffu, h->ws_bytes / 4, st);
     else if (o.debug & SKEW_EVD_DEBUG_ZERO_WS) skew::launch_fill32(h->ws, 0u, h->ws_bytes / 4, st);
@@ -1160,7 +1197,19 @@ int solve(skew_evd_handle h, int n, const double *A, int lda, int nev, double *l
     } else {
         rc = prec ? stage_band<float>(h, p, L, A, lda, 1) : stage_band<double>(h, p, L, A, lda, 1);
         if (rc) return rc;
+        const bool early_m = n >= EARLY_TFAC_MIN_N && p.ngroups > 0 && merged_bt1(p);
+        if (early_m) {
+            rc = ensure_aux(h);
+            if (rc) return rc;
+            HCHK(hipEventRecord(h->aux_ev[3], st));   // stage 1 queued
+        }
         rc = stage_chase(h, p, L);
+        if (rc) return rc;
+        if (early_m) {
+            rc = start_bt1_merges(h, p, L);
+            if (rc) return rc;
+            h->merges_started = true;
+        }
     }
     if (rc) return rc;
     rec[1] = rec[2] = rec[3] = true;

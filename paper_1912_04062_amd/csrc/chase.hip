@@ -376,6 +376,7 @@ int chase_ngroups(int n, int b, int nb2, int *goff_host)
 // flight at once (a sweep of n/b steps starts about every second step of its
 // predecessor, so about n/(2b) are in flight) with room to spare, so that a
 // sweep never waits for a free workgroup; never more than the device holds.
+// The CUs left free take other streams' work meanwhile.
 int chase_workgroups(int n, int b)
 {
     int dev = 0, ncu = 256;
@@ -385,7 +386,7 @@ int chase_workgroups(int n, int b)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_bulge_chase, 256, 0);
     if (occ < 1) occ = 1;
     int G = ncu * occ;
-    const int inflight = n / (b > 0 ? b : 1) + 16;
+    const int inflight = n / (2 * (b > 0 ? b : 1)) + 16;
     if (G > inflight) G = inflight;
     if (G > n - 2) G = n - 2;
     if (G < 1) G = 1;
