@@ -573,7 +573,7 @@ __global__ __launch_bounds__(256) void k_bt2_win(double *__restrict__ Z, int ldz
 // is capped so that two waves share every SIMD):
 //   k_bt1_w   Wp[s] = V^T Z over the s-th chunk of rows (split K)
 //   k_bt1_t   W2 = T * sum_s Wp[s]
-//   k_bt1_z   Z -= V W2 on 128 x 64 tiles.
+//   k_bt1_z   Z -= V W2 on 64 x 128 tiles (taller tiles measured slower).
 
 // Element (row, k) of the (merged) V of a block: column k < b1 comes from V1
 // (m rows), k >= b1 from V2 (m2 rows, starting b1 rows lower); 0 elsewhere.
@@ -641,7 +641,7 @@ template <typename T, int KK>
 __global__ __launch_bounds__(256) GEMM_OCC2 void k_bt1_z(
     T *__restrict__ Z, int ldz, int ncols, MergedV<T> V, const T *__restrict__ W2)
 {
-    constexpr int TM = 128, TN = 64;
+    constexpr int TM = 64, TN = 128;
     extern __shared__ char smraw[];
     T *smem = (T *)smraw;
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
@@ -997,8 +997,8 @@ static void bt1_block(T *Z, int ldz, int m, int ncols, MergedV<T> V, const doubl
                        (const T *)Z, ldz, ncols, V, kc, Wp);
     hipLaunchKernelGGL((k_bt1_t<T, KK>), dim3(cdiv(ncols, 64)), dim3(256), (gemm::smem_bytes<T, KK, 64>()), st, Tm,
                        (const double *)Wp, S, ncols, W2);
-    hipLaunchKernelGGL((k_bt1_z<T, KK>), dim3(cdiv(m, 128), cdiv(ncols, 64)), dim3(256),
-                       (gemm::smem_bytes<T, 128, 64>()), st, Z, ldz, ncols, V, (const T *)W2);
+    hipLaunchKernelGGL((k_bt1_z<T, KK>), dim3(cdiv(m, 64), cdiv(ncols, 128)), dim3(256),
+                       (gemm::smem_bytes<T, 64, 128>()), st, Z, ldz, ncols, V, (const T *)W2);
 }
 
 template <typename T>
